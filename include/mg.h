@@ -1,0 +1,183 @@
+/*
+ * mg.h - C ABI of the MI355X multigrid pressure-projection solver.
+ *
+ * The library solves the pressure Poisson equation of the free-surface flow solver
+ * (paper section 2, eq. (pois); finite-volume form eq. (integral2)):
+ *
+ *     div( (1/rho) grad p ) = f
+ *
+ * on a uniform cell-centred N x N x N grid with spacing h, periodic in x and y and
+ * with walls (zero normal flux) at both z ends, with an immersed body whose faces
+ * carry no flux.  Discrete operator, for every fluid cell c:
+ *
+ *     (A p)_c = h^-2 * sum over the six faces f of c of beta_f (p_neighbour - p_c)
+ *
+ * where beta_f is the face product "1/rho times open area" that section 3.1 forms on
+ * the finest grid and moves to the coarse grids as one unit.  The method is geometric
+ * multigrid (section 3.1): V(2,2) cycles of red-black Gauss-Seidel, 8-child mean
+ * restriction, trilinear prolongation, face-product coarsening (mean of the 4
+ * coincident fine faces) down to 4^3, and an FP64 pseudo-inverse solve there.
+ *
+ * Layout.  Every array pointer is a DEVICE pointer to a C-contiguous [N][N][N] array
+ * indexed [k][j][i] (x fastest), unless marked HOST.  Face arrays use low-face
+ * storage: bx[k][j][i] couples cells (i-1 mod N, j, k) and (i, j, k); by likewise
+ * in j; bz[k][j][i] couples (i, j, k-1) and (i, j, k), so bz[0][..] is the bottom wall
+ * (forced to 0) and the top wall is implicit.  mask: 1 = fluid, 0 = body.
+ * Batched arrays are [batch][N][N][N].
+ *
+ * Ownership.  The caller owns every array and the workspace (device memory of
+ * mg_workspace_size() bytes, 256-byte aligned).  The library never allocates device
+ * memory.  mg_setup copies the finest coefficients into the workspace, so the caller
+ * may free or reuse its beta arrays afterwards; the workspace must outlive the
+ * context.  A context is not thread-safe; distinct contexts are independent.
+ *
+ * Streams.  All device work is ordered on the HIP stream given to mg_setup (or set
+ * later with mg_set_stream); NULL means the default stream.  Entry points that
+ * report numbers to the host (mg_setup, mg_solve) synchronise that stream.
+ *
+ * Errors.  Every int-returning function returns MG_OK or a negative code and never
+ * throws across the ABI; mg_last_error() returns a thread-local message.  Invalid
+ * arguments are detected on the host before any device work is queued.
+ */
+#ifndef MG_H
+#define MG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mg_ctx mg_ctx;
+
+enum {
+  MG_OK = 0,
+  MG_EINVAL = -1,      /* bad dims, pointer, tolerance, flags, or beta < 0 / non-finite */
+  MG_EWORKSPACE = -2,  /* workspace NULL, misaligned or smaller than mg_workspace_size */
+  MG_EHIP = -3,        /* a HIP runtime call failed (message names it) */
+  MG_ENOCONV = -4,     /* max_cycles reached before tol; p holds the last iterate */
+  MG_EBREAKDOWN = -5   /* residual non-finite or grew 1e3-fold; p holds the last iterate */
+};
+
+/* mg_setup flags */
+enum {
+  MG_FP64 = 0,   /* FP64 V-cycles */
+  MG_MIXED = 1   /* FP32 V-cycles inside FP64 iterative refinement (FP64 residual,
+                    update and coarsest solve); the workspace also holds FP32 copies */
+};
+
+/* precision selector of the component entry points */
+enum { MG_PREC_F64 = 0, MG_PREC_F32 = 1 };
+
+/* smoothing order of mg_smooth */
+enum { MG_PRE = 0 /* red then black */, MG_POST = 1 /* black then red */ };
+
+typedef struct {
+  int cycles;           /* V-cycles (FP64) or refinement steps (mixed), summed over the batch */
+  int levels;           /* grids in the hierarchy, finest N down to 4 */
+  long long active_cells;  /* fluid cells with at least one open face on the finest grid */
+  long long dropped_cells; /* fluid cells with no open face: no equation, treated as body */
+  double removed_mean;  /* fluid mean removed from f (last batch item) */
+  double final_relres;  /* ||P f - A p|| / ||P f|| at exit (largest over the batch) */
+  double seconds;       /* host wall time of the call */
+  size_t ws_bytes;      /* workspace bytes in use */
+} mg_stats;
+
+/*
+ * Workspace bytes for an N^3 grid (dims[0] = dims[1] = dims[2] = N, N a power of two,
+ * 8 <= N <= 1024) with the given flags, or 0 if the arguments are invalid.
+ * Pure host arithmetic: callable without a GPU.
+ */
+size_t mg_workspace_size(const int dims[3], int flags);
+
+/*
+ * Face coefficients from cell density (eq. (density) gives rho from the VOF fraction;
+ * section 3.1 forms 1/rho times the open area on the faces of the finest grid):
+ *     beta_f = o_f * 2 / (rho_L + rho_R),   o_f = mask_L * mask_R,   z walls 0.
+ * rho > 0 in fluid cells (body values unused).  Writes bx, by, bz (caller-owned).
+ */
+int mg_coeffs_from_rho(const double* rho, const uint8_t* mask, const int dims[3],
+                       double* bx, double* by, double* bz, void* hip_stream);
+
+/*
+ * Build the multigrid hierarchy (section 3.1): copy the finest face products into
+ * the workspace, zero faces touching the body and the bottom wall, mark fluid cells
+ * with no open face inactive, coarsen the face products level by level (coarse face
+ * = mean of its 4 fine faces, coarse cell active if any child is and it keeps an open
+ * face), and form the FP64 pseudo-inverse of the 4^3 operator on the host.
+ * beta must be >= 0 and finite; h > 0.  On success *out is a new context.
+ */
+int mg_setup(mg_ctx** out, void* workspace, size_t ws_bytes,
+             const double* bx, const double* by, const double* bz,
+             const uint8_t* mask, const int dims[3], double h, int flags, void* hip_stream);
+
+/* Change the stream used by later calls on this context. */
+int mg_set_stream(mg_ctx* ctx, void* hip_stream);
+
+/*
+ * Solve A p_b = P f_b for b = 0..batch-1 (P removes the fluid mean of f; section 3.1
+ * method, V(2,2) cycles until ||P f - A p||_2 / ||P f||_2 <= tol, checked after every
+ * cycle or refinement step).  p is in/out: initial guess in, solution out, with zero
+ * fluid mean and 0 in the body.  hist (HOST, may be NULL) receives batch rows of
+ * max_cycles+1 relative residuals, hist[b*(max_cycles+1)+0] for the initial guess;
+ * n_hist (HOST, may be NULL) receives the entries written per item.  stats may be NULL.
+ * Returns MG_ENOCONV / MG_EBREAKDOWN with p and hist valid when a solve stops early.
+ */
+int mg_solve(mg_ctx* ctx, const double* f, double* p, int batch, double tol, int max_cycles,
+             double* hist, int* n_hist, mg_stats* stats);
+
+/* Ap_b = A p_b on the finest grid (0 in the body). */
+int mg_apply(mg_ctx* ctx, const double* p, double* Ap, int batch);
+
+/*
+ * Gradient of L through the solve (adjoint method; the paper does not differentiate):
+ * with p_b the solutions and mu_b the adjoint solutions (A mu_b = P dL/dp_b),
+ *     g_f = o_f h^-2 sum_b (mu_b,R - mu_b,L)(p_b,R - p_b,L)          (= dL/dbeta_f)
+ *     grho_c = -1/2 sum over the faces f of c of beta_f^2 g_f          (= dL/drho_c)
+ * the second valid when beta came from mg_coeffs_from_rho.  Any of gbx, gby, gbz,
+ * grho may be NULL to skip it.  Outputs are overwritten, not accumulated.
+ */
+int mg_coeff_grad(mg_ctx* ctx, const double* mu, const double* p, int batch,
+                  double* gbx, double* gby, double* gbz, double* grho);
+
+void mg_destroy(mg_ctx* ctx);
+
+/* Thread-local message describing the last failure on this thread ("" if none). */
+const char* mg_last_error(void);
+
+/* ---------------------------------------------------------------------------------
+ * Component entry points: single steps of the V-cycle on one level of an existing
+ * hierarchy, for verification and per-kernel timing.  prec selects FP64 (double*)
+ * or FP32 (float*, MIXED contexts only) arrays; level 0 is the finest grid.
+ * Arrays are caller-owned device arrays of the level's size.
+ * ------------------------------------------------------------------------------ */
+
+/* Size and spacing of one grid; returns the number of grids (> 0) or an error code. */
+int mg_level_info(mg_ctx* ctx, int level, int* n, double* h);
+
+/* Copy a level's face coefficients (FP64) and activity mask out of the hierarchy. */
+int mg_level_coeffs(mg_ctx* ctx, int level, double* bx, double* by, double* bz, uint8_t* mask);
+
+/* `sweeps` red-black Gauss-Seidel sweeps on level `level` for A p = f, order MG_PRE
+ * (red then black) or MG_POST (black then red); red = (i+j+k) even. */
+int mg_smooth(mg_ctx* ctx, int prec, int level, void* p, const void* f, int sweeps, int order);
+
+/* fc = 8-child mean of r = f - A p on level `level`, written at level+1 size. */
+int mg_residual_restrict(mg_ctx* ctx, int prec, int level, const void* p, const void* f, void* fc);
+
+/* p += mask * trilinear(ec): ec at level+1 size, p at level `level`. */
+int mg_prolong_add(mg_ctx* ctx, int prec, int level, const void* ec, void* p);
+
+/* e = A_c^+ (f - fluid mean of f) on the coarsest grid, in FP64 whatever prec. */
+int mg_coarse_solve(mg_ctx* ctx, int prec, const void* f, void* e);
+
+/* One V(2,2) cycle on the finest grid for A p = f, f already compatible (FP32 cycles
+ * with prec = MG_PREC_F32 on MIXED contexts). */
+int mg_vcycle(mg_ctx* ctx, int prec, void* p, const void* f);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MG_H */

@@ -1,0 +1,543 @@
+// C ABI and host driver of the multigrid pressure solve (declared in include/mg.h).
+//
+// The host side plans the hierarchy, carves the caller's workspace, queues kernels
+// on the caller's stream and reads back one scalar (the residual norm) per cycle.
+// It never allocates device memory; the only host allocation besides the context
+// object is a small pinned buffer for those read-backs.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "mg.h"
+#include "mg_kernels.h"
+#include "mg_plan.h"
+
+namespace mg {
+void symmetric_pinv(int n, std::vector<double>& a, double rtol, std::vector<double>& pinv);
+}
+
+namespace {
+
+thread_local std::string g_error;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_error = buf;
+  return code;
+}
+
+#define MG_HIP(call)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess) return fail(MG_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+#define MG_TRY(call)          \
+  do {                        \
+    int rc_ = (call);         \
+    if (rc_ != MG_OK) return rc_; \
+  } while (0)
+
+constexpr double kPinvRtol = 1e-12;
+constexpr double kBreakdownGrowth = 1e3;
+
+// device scalar slots
+enum { S_FMEAN = 0, S_FNORM2 = 1, S_RNORM2 = 2, S_PMEAN = 3, S_COUNT = 8 };
+
+struct Level {
+  int n = 0, q = 0;
+  double h = 0;
+  double *bx = nullptr, *by = nullptr, *bz = nullptr, *f = nullptr, *e = nullptr, *t = nullptr;
+  uint8_t* mask = nullptr;
+  float *bx32 = nullptr, *by32 = nullptr, *bz32 = nullptr, *f32 = nullptr, *e32 = nullptr, *t32 = nullptr;
+};
+
+template <typename T>
+struct View {
+  T *bx, *by, *bz, *f, *e, *t;
+};
+
+}  // namespace
+
+struct mg_ctx {
+  mg::Plan plan;
+  int flags = 0;
+  int L = 0;
+  Level lv[mg::kMaxLevels];
+  hipStream_t stream = nullptr;
+  unsigned char* ws = nullptr;
+  double* pinv = nullptr;
+  double* partials = nullptr;
+  double* scal = nullptr;
+  long long* counters = nullptr;
+  double* host = nullptr;   // pinned, S_COUNT doubles
+  long long active = 0, dropped = 0;
+
+  View<double> v64(int l) const {
+    const Level& a = lv[l];
+    return {a.bx, a.by, a.bz, a.f, a.e, a.t};
+  }
+  View<float> v32(int l) const {
+    const Level& a = lv[l];
+    return {a.bx32, a.by32, a.bz32, a.f32, a.e32, a.t32};
+  }
+  template <typename T>
+  View<T> view(int l) const;
+};
+
+template <>
+View<double> mg_ctx::view<double>(int l) const { return v64(l); }
+template <>
+View<float> mg_ctx::view<float>(int l) const { return v32(l); }
+
+namespace {
+
+template <typename T>
+T* at(unsigned char* ws, size_t off) {
+  return off == mg::kAbsent ? nullptr : reinterpret_cast<T*>(ws + off);
+}
+
+long long cells(const Level& a) { return static_cast<long long>(a.n) * a.n * a.n; }
+
+// ---------------------------------------------------------------- V-cycle (T = double/float)
+
+template <typename T>
+int smooth(mg_ctx* c, int l, T* p, const T* f, const double* fshift, int sweeps, int order) {
+  const Level& a = c->lv[l];
+  const View<T> v = c->view<T>(l);
+  for (int s = 0; s < sweeps; ++s) {
+    for (int half = 0; half < 2; ++half) {
+      const int colour = (order == MG_PRE) ? half : 1 - half;   // red = 0 first when pre-smoothing
+      MG_HIP(mg::launch_rbgs_half<T>(p, f, v.bx, v.by, v.bz, a.q, a.h, colour, fshift, c->stream));
+    }
+  }
+  return MG_OK;
+}
+
+template <typename T>
+int residual_restrict(mg_ctx* c, int l, const T* p, const T* f, const double* fshift, T* fc, T* ec) {
+  const Level& a = c->lv[l];
+  const View<T> v = c->view<T>(l);
+  MG_HIP(mg::launch_residual_restrict<T>(p, f, v.bx, v.by, v.bz, a.q, a.h, fshift, fc, ec, c->stream));
+  return MG_OK;
+}
+
+template <typename T>
+int vcycle(mg_ctx* c, int l, T* p, const T* f, const double* fshift) {
+  if (l == c->L - 1) {
+    MG_HIP(mg::launch_coarse_solve<T>(f, p, c->pinv, c->lv[l].mask, c->stream));
+    return MG_OK;
+  }
+  const View<T> next = c->view<T>(l + 1);
+  MG_TRY(smooth<T>(c, l, p, f, fshift, 2, MG_PRE));
+  MG_TRY(residual_restrict<T>(c, l, p, f, fshift, next.f, next.e));
+  MG_TRY(vcycle<T>(c, l + 1, next.e, next.f, nullptr));
+  MG_HIP(mg::launch_prolong_add<T>(next.e, p, c->lv[l].mask, c->lv[l].q, c->stream));
+  MG_TRY(smooth<T>(c, l, p, f, fshift, 2, MG_POST));
+  return MG_OK;
+}
+
+// ---------------------------------------------------------------- reductions
+
+int reduce(mg_ctx* c, int nparts, double scale, int slot) {
+  MG_HIP(mg::launch_reduce_final(c->partials, nparts, scale, c->scal + slot, c->stream));
+  return MG_OK;
+}
+
+int read_scalars(mg_ctx* c, double* out, int count) {
+  MG_HIP(hipMemcpyAsync(c->host, c->scal, sizeof(double) * count, hipMemcpyDeviceToHost, c->stream));
+  MG_HIP(hipStreamSynchronize(c->stream));
+  std::memcpy(out, c->host, sizeof(double) * count);
+  return MG_OK;
+}
+
+// ||r||^2 of the finest residual into scal[S_RNORM2]; optional FP32 copy of r
+int residual_norm(mg_ctx* c, const double* p, const double* f, const double* fshift, float* r32, float* e32) {
+  const Level& a = c->lv[0];
+  int nb = 0;
+  MG_HIP(mg::launch_residual_norm(p, f, a.bx, a.by, a.bz, a.q, a.h, fshift, r32, e32, c->partials, &nb, c->stream));
+  return reduce(c, nb, 1.0, S_RNORM2);
+}
+
+int check_prec(mg_ctx* c, int prec) {
+  if (prec != MG_PREC_F64 && prec != MG_PREC_F32) return fail(MG_EINVAL, "prec must be MG_PREC_F64 or MG_PREC_F32");
+  if (prec == MG_PREC_F32 && !(c->flags & MG_MIXED))
+    return fail(MG_EINVAL, "FP32 arrays exist only in contexts set up with MG_MIXED");
+  return MG_OK;
+}
+
+// One right-hand side.  hist has room for max_cycles + 1 entries.
+int solve_one(mg_ctx* c, const double* f, double* p, double tol, int max_cycles, double* hist, int* n_hist,
+              double* removed_mean, double* final_relres, int* cycles) {
+  const Level& a = c->lv[0];
+  const double* fshift = c->scal + S_FMEAN;
+  int nb = 0;
+  // P f: fluid mean of f (applied on the fly by every finest-grid kernel) and ||P f||
+  MG_HIP(mg::launch_masked_sum(f, a.mask, a.q, 0, nullptr, c->partials, &nb, c->stream));
+  MG_TRY(reduce(c, nb, 1.0 / static_cast<double>(c->active), S_FMEAN));
+  MG_HIP(mg::launch_masked_sum(f, a.mask, a.q, 1, fshift, c->partials, &nb, c->stream));
+  MG_TRY(reduce(c, nb, 1.0, S_FNORM2));
+  MG_HIP(mg::launch_gauge(p, a.mask, a.q, nullptr, c->stream));   // initial guess: 0 in the body
+  const bool mixed = (c->flags & MG_MIXED) != 0;
+  // the residual pass also leaves the FP32 copy of r that the next FP32 cycle solves for
+  float* r32 = mixed ? a.f32 : nullptr;
+  float* e32 = mixed ? a.e32 : nullptr;
+  MG_TRY(residual_norm(c, p, f, fshift, r32, e32));
+  double s[3];
+  MG_TRY(read_scalars(c, s, 3));
+  *removed_mean = s[S_FMEAN];
+  const double nf = std::sqrt(s[S_FNORM2]);
+  int nh = 0;
+  *cycles = 0;
+  if (!(nf > 0.0)) {   // P f = 0: the solution is p = 0
+    MG_HIP(hipMemsetAsync(p, 0, sizeof(double) * cells(a), c->stream));
+    if (hist) hist[0] = 0.0;
+    *n_hist = 1;
+    *final_relres = 0.0;
+    return std::isfinite(nf) ? MG_OK : fail(MG_EBREAKDOWN, "right-hand side is not finite");
+  }
+  double r = std::sqrt(s[S_RNORM2]) / nf;
+  const double r0 = r;
+  if (hist) hist[nh] = r;
+  ++nh;
+  int status = MG_OK;
+  while (std::isfinite(r) && r > tol && *cycles < max_cycles) {
+    if (mixed) {
+      // FP32 V-cycle for the correction from the FP32 copy of the FP64 residual, FP64 update
+      MG_TRY(vcycle<float>(c, 0, e32, r32, nullptr));
+      MG_HIP(mg::launch_update_p(p, e32, a.mask, a.q, c->stream));
+    } else {
+      MG_TRY(vcycle<double>(c, 0, p, f, fshift));
+    }
+    ++*cycles;
+    MG_TRY(residual_norm(c, p, f, fshift, r32, e32));
+    double sn[3];
+    MG_TRY(read_scalars(c, sn, 3));
+    r = std::sqrt(sn[S_RNORM2]) / nf;
+    if (hist) hist[nh] = r;
+    ++nh;
+    if (!std::isfinite(r) || r > kBreakdownGrowth * std::fmax(r0, 1.0)) {
+      status = fail(MG_EBREAKDOWN, "residual %g after %d cycles (initial %g)", r, *cycles, r0);
+      break;
+    }
+  }
+  if (status == MG_OK && r > tol)
+    status = fail(MG_ENOCONV, "relative residual %g > tol %g after %d cycles", r, tol, *cycles);
+  // gauge: zero fluid mean, 0 in the body
+  MG_HIP(mg::launch_masked_sum(p, a.mask, a.q, 0, nullptr, c->partials, &nb, c->stream));
+  MG_TRY(reduce(c, nb, 1.0 / static_cast<double>(c->active), S_PMEAN));
+  MG_HIP(mg::launch_gauge(p, a.mask, a.q, c->scal + S_PMEAN, c->stream));
+  *n_hist = nh;
+  *final_relres = r;
+  return status;
+}
+
+// dense operator of the coarsest grid (host), column-major = row-major (symmetric)
+void coarse_dense(const std::vector<double>& bx, const std::vector<double>& by, const std::vector<double>& bz,
+                  const std::vector<uint8_t>& mask, int n, double h, std::vector<double>& A) {
+  const int nc = n * n * n;
+  A.assign(static_cast<size_t>(nc) * nc, 0.0);
+  const double ih2 = 1.0 / (h * h);
+  auto id = [n](int i, int j, int k) { return (k * n + j) * n + i; };
+  for (int k = 0; k < n; ++k)
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i) {
+        const int c = id(i, j, k);
+        if (!mask[c]) continue;
+        const int nb[6] = {id((i + n - 1) % n, j, k), id((i + 1) % n, j, k), id(i, (j + n - 1) % n, k),
+                           id(i, (j + 1) % n, k), k > 0 ? id(i, j, k - 1) : c, k < n - 1 ? id(i, j, k + 1) : c};
+        const double b[6] = {bx[c], bx[nb[1]], by[c], by[nb[3]], bz[c], k < n - 1 ? bz[nb[5]] : 0.0};
+        for (int f = 0; f < 6; ++f) {
+          if (b[f] == 0.0) continue;
+          A[static_cast<size_t>(c) * nc + nb[f]] += b[f] * ih2;
+          A[static_cast<size_t>(c) * nc + c] -= b[f] * ih2;
+        }
+      }
+}
+
+int check_level(mg_ctx* c, int level, int need_coarser) {
+  if (!c) return fail(MG_EINVAL, "null context");
+  if (level < 0 || level >= c->L - need_coarser) return fail(MG_EINVAL, "level %d out of range", level);
+  return MG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mg_last_error(void) { return g_error.c_str(); }
+
+size_t mg_workspace_size(const int dims[3], int flags) {
+  int n = 0;
+  mg::Plan plan;
+  if (mg::validate_dims(dims, &n) != 0 || mg::build_plan(n, flags, &plan) != 0) return 0;
+  return plan.total;
+}
+
+int mg_coeffs_from_rho(const double* rho, const uint8_t* mask, const int dims[3], double* bx, double* by, double* bz,
+                       void* hip_stream) {
+  int n = 0;
+  if (mg::validate_dims(dims, &n) != 0) return fail(MG_EINVAL, "dims must be equal powers of two in [8, 1024]");
+  if (!rho || !mask || !bx || !by || !bz) return fail(MG_EINVAL, "null array pointer");
+  int q = 0;
+  while ((1 << q) < n) ++q;
+  MG_HIP(mg::launch_coeffs_from_rho(rho, mask, q, bx, by, bz, static_cast<hipStream_t>(hip_stream)));
+  return MG_OK;
+}
+
+int mg_setup(mg_ctx** out, void* workspace, size_t ws_bytes, const double* bx, const double* by, const double* bz,
+             const uint8_t* mask, const int dims[3], double h, int flags, void* hip_stream) {
+  if (!out) return fail(MG_EINVAL, "null output pointer");
+  *out = nullptr;
+  int n = 0;
+  if (mg::validate_dims(dims, &n) != 0) return fail(MG_EINVAL, "dims must be equal powers of two in [8, 1024]");
+  if (!bx || !by || !bz || !mask) return fail(MG_EINVAL, "null array pointer");
+  if (!(h > 0.0) || !std::isfinite(h)) return fail(MG_EINVAL, "h must be positive and finite");
+  if (flags != MG_FP64 && flags != MG_MIXED) return fail(MG_EINVAL, "unknown flags %d", flags);
+  mg::Plan plan;
+  if (mg::build_plan(n, flags, &plan) != 0) return fail(MG_EINVAL, "unsupported grid");
+  if (!workspace) return fail(MG_EWORKSPACE, "null workspace");
+  if (reinterpret_cast<uintptr_t>(workspace) % mg::kAlign != 0) return fail(MG_EWORKSPACE, "workspace not 256-byte aligned");
+  if (ws_bytes < plan.total) return fail(MG_EWORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes, plan.total);
+
+  mg_ctx* c = new mg_ctx;
+  c->plan = plan;
+  c->flags = flags;
+  c->L = plan.levels;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->ws = static_cast<unsigned char*>(workspace);
+  for (int l = 0; l < c->L; ++l) {
+    const mg::LevelPlan& lp = plan.lv[l];
+    Level& a = c->lv[l];
+    a.n = lp.n;
+    a.q = lp.log2n;
+    a.h = std::ldexp(h, l);
+    a.bx = at<double>(c->ws, lp.bx);
+    a.by = at<double>(c->ws, lp.by);
+    a.bz = at<double>(c->ws, lp.bz);
+    a.mask = at<uint8_t>(c->ws, lp.mask);
+    a.f = at<double>(c->ws, lp.f);
+    a.e = at<double>(c->ws, lp.e);
+    a.t = at<double>(c->ws, lp.t);
+    a.bx32 = at<float>(c->ws, lp.bx32);
+    a.by32 = at<float>(c->ws, lp.by32);
+    a.bz32 = at<float>(c->ws, lp.bz32);
+    a.f32 = at<float>(c->ws, lp.f32);
+    a.e32 = at<float>(c->ws, lp.e32);
+    a.t32 = at<float>(c->ws, lp.t32);
+  }
+  c->pinv = at<double>(c->ws, plan.pinv);
+  c->partials = at<double>(c->ws, plan.partials);
+  c->scal = at<double>(c->ws, plan.scalars);
+  c->counters = at<long long>(c->ws, plan.counters);
+
+  auto cleanup = [&](int rc) {
+    mg_destroy(c);
+    return rc;
+  };
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->host), sizeof(double) * S_COUNT * 2, hipHostMallocDefault) !=
+      hipSuccess) {
+    c->host = nullptr;
+    return cleanup(fail(MG_EHIP, "hipHostMalloc of the read-back buffer failed"));
+  }
+  hipStream_t s = c->stream;
+  int rc = MG_OK;
+  auto hip = [&](hipError_t e, const char* what) {
+    if (e != hipSuccess && rc == MG_OK) rc = fail(MG_EHIP, "%s: %s", what, hipGetErrorString(e));
+  };
+  hip(hipMemsetAsync(c->counters, 0, 16 * sizeof(long long), s), "hipMemsetAsync(counters)");
+  Level& f0 = c->lv[0];
+  hip(mg::launch_setup_fine(bx, by, bz, mask, f0.q, f0.bx, f0.by, f0.bz, f0.mask, c->counters, s), "setup_fine");
+  for (int l = 1; l < c->L; ++l) {
+    const Level& a = c->lv[l - 1];
+    Level& b = c->lv[l];
+    hip(mg::launch_coarsen(a.bx, a.by, a.bz, a.mask, b.q, b.bx, b.by, b.bz, b.mask, s), "coarsen");
+  }
+  if (flags & MG_MIXED) {
+    for (int l = 0; l < c->L; ++l) {
+      const Level& a = c->lv[l];
+      hip(mg::launch_to_f32(a.bx, a.bx32, cells(a), s), "to_f32");
+      hip(mg::launch_to_f32(a.by, a.by32, cells(a), s), "to_f32");
+      hip(mg::launch_to_f32(a.bz, a.bz32, cells(a), s), "to_f32");
+    }
+  }
+  // coarsest operator to the host, FP64 pseudo-inverse back to the device
+  const Level& cl = c->lv[c->L - 1];
+  const int nc = static_cast<int>(cells(cl));
+  std::vector<double> hbx(nc), hby(nc), hbz(nc), A, P;
+  std::vector<uint8_t> hm(nc);
+  long long cnt[3] = {0, 0, 0};
+  hip(hipMemcpyAsync(hbx.data(), cl.bx, nc * sizeof(double), hipMemcpyDeviceToHost, s), "copy coarse bx");
+  hip(hipMemcpyAsync(hby.data(), cl.by, nc * sizeof(double), hipMemcpyDeviceToHost, s), "copy coarse by");
+  hip(hipMemcpyAsync(hbz.data(), cl.bz, nc * sizeof(double), hipMemcpyDeviceToHost, s), "copy coarse bz");
+  hip(hipMemcpyAsync(hm.data(), cl.mask, nc, hipMemcpyDeviceToHost, s), "copy coarse mask");
+  hip(hipMemcpyAsync(cnt, c->counters, sizeof cnt, hipMemcpyDeviceToHost, s), "copy counters");
+  hip(hipStreamSynchronize(s), "hipStreamSynchronize(setup)");
+  if (rc != MG_OK) return cleanup(rc);
+  if (cnt[0] > 0) return cleanup(fail(MG_EINVAL, "%lld face coefficients are negative or not finite", cnt[0]));
+  if (cnt[1] == 0) return cleanup(fail(MG_EINVAL, "no fluid cell has an open face"));
+  c->active = cnt[1];
+  c->dropped = cnt[2];
+  coarse_dense(hbx, hby, hbz, hm, cl.n, cl.h, A);
+  mg::symmetric_pinv(nc, A, kPinvRtol, P);
+  hip(hipMemcpyAsync(c->pinv, P.data(), P.size() * sizeof(double), hipMemcpyHostToDevice, s), "upload pinv");
+  hip(hipStreamSynchronize(s), "hipStreamSynchronize(pinv)");
+  if (rc != MG_OK) return cleanup(rc);
+  *out = c;
+  return MG_OK;
+}
+
+int mg_set_stream(mg_ctx* ctx, void* hip_stream) {
+  if (!ctx) return fail(MG_EINVAL, "null context");
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  return MG_OK;
+}
+
+int mg_solve(mg_ctx* ctx, const double* f, double* p, int batch, double tol, int max_cycles, double* hist,
+             int* n_hist, mg_stats* stats) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!ctx) return fail(MG_EINVAL, "null context");
+  if (!f || !p) return fail(MG_EINVAL, "null array pointer");
+  if (batch < 1) return fail(MG_EINVAL, "batch must be >= 1");
+  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(MG_EINVAL, "tol must be positive and finite");
+  if (max_cycles < 0) return fail(MG_EINVAL, "max_cycles must be >= 0");
+  const long long n3 = cells(ctx->lv[0]);
+  int status = MG_OK, total_cycles = 0;
+  double removed = 0.0, worst = 0.0;
+  for (int b = 0; b < batch; ++b) {
+    int nh = 0, cyc = 0;
+    double rm = 0.0, fr = 0.0;
+    double* hb = hist ? hist + static_cast<long long>(b) * (max_cycles + 1) : nullptr;
+    const int rc = solve_one(ctx, f + b * n3, p + b * n3, tol, max_cycles, hb, &nh, &rm, &fr, &cyc);
+    if (n_hist) n_hist[b] = nh;
+    total_cycles += cyc;
+    removed = rm;
+    worst = std::fmax(worst, fr);
+    if (rc == MG_EINVAL || rc == MG_EHIP) return rc;
+    if (rc != MG_OK && status == MG_OK) status = rc;
+  }
+  if (stats) {
+    stats->cycles = total_cycles;
+    stats->levels = ctx->L;
+    stats->active_cells = ctx->active;
+    stats->dropped_cells = ctx->dropped;
+    stats->removed_mean = removed;
+    stats->final_relres = worst;
+    stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    stats->ws_bytes = ctx->plan.total;
+  }
+  return status;
+}
+
+int mg_apply(mg_ctx* ctx, const double* p, double* Ap, int batch) {
+  if (!ctx) return fail(MG_EINVAL, "null context");
+  if (!p || !Ap || batch < 1) return fail(MG_EINVAL, "bad arguments");
+  const Level& a = ctx->lv[0];
+  for (int b = 0; b < batch; ++b)
+    MG_HIP(mg::launch_apply(p + b * cells(a), a.bx, a.by, a.bz, a.q, a.h, Ap + b * cells(a), ctx->stream));
+  return MG_OK;
+}
+
+int mg_coeff_grad(mg_ctx* ctx, const double* mu, const double* p, int batch, double* gbx, double* gby, double* gbz,
+                  double* grho) {
+  if (!ctx) return fail(MG_EINVAL, "null context");
+  if (!mu || !p || batch < 1) return fail(MG_EINVAL, "bad arguments");
+  const Level& a = ctx->lv[0];
+  MG_HIP(mg::launch_coeff_grad(mu, p, batch, a.bx, a.by, a.bz, a.mask, a.q, a.h, gbx, gby, gbz, grho, ctx->stream));
+  return MG_OK;
+}
+
+void mg_destroy(mg_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->host) (void)hipHostFree(ctx->host);
+  delete ctx;
+}
+
+int mg_level_info(mg_ctx* ctx, int level, int* n, double* h) {
+  MG_TRY(check_level(ctx, level, 0));
+  if (n) *n = ctx->lv[level].n;
+  if (h) *h = ctx->lv[level].h;
+  return ctx->L;
+}
+
+int mg_level_coeffs(mg_ctx* ctx, int level, double* bx, double* by, double* bz, uint8_t* mask) {
+  MG_TRY(check_level(ctx, level, 0));
+  const Level& a = ctx->lv[level];
+  const size_t nb = sizeof(double) * cells(a);
+  if (bx) MG_HIP(hipMemcpyAsync(bx, a.bx, nb, hipMemcpyDeviceToDevice, ctx->stream));
+  if (by) MG_HIP(hipMemcpyAsync(by, a.by, nb, hipMemcpyDeviceToDevice, ctx->stream));
+  if (bz) MG_HIP(hipMemcpyAsync(bz, a.bz, nb, hipMemcpyDeviceToDevice, ctx->stream));
+  if (mask) MG_HIP(hipMemcpyAsync(mask, a.mask, cells(a), hipMemcpyDeviceToDevice, ctx->stream));
+  return MG_OK;
+}
+
+int mg_smooth(mg_ctx* ctx, int prec, int level, void* p, const void* f, int sweeps, int order) {
+  MG_TRY(check_level(ctx, level, 0));
+  MG_TRY(check_prec(ctx, prec));
+  if (!p || !f || sweeps < 0 || (order != MG_PRE && order != MG_POST)) return fail(MG_EINVAL, "bad arguments");
+  if (prec == MG_PREC_F64)
+    return smooth<double>(ctx, level, static_cast<double*>(p), static_cast<const double*>(f), nullptr, sweeps, order);
+  return smooth<float>(ctx, level, static_cast<float*>(p), static_cast<const float*>(f), nullptr, sweeps, order);
+}
+
+int mg_residual_restrict(mg_ctx* ctx, int prec, int level, const void* p, const void* f, void* fc) {
+  MG_TRY(check_level(ctx, level, 1));
+  MG_TRY(check_prec(ctx, prec));
+  if (!p || !f || !fc) return fail(MG_EINVAL, "null array pointer");
+  if (prec == MG_PREC_F64) {
+    const View<double> nx = ctx->v64(level + 1);
+    return residual_restrict<double>(ctx, level, static_cast<const double*>(p), static_cast<const double*>(f),
+                                     nullptr, static_cast<double*>(fc), nx.t);
+  }
+  const View<float> nx = ctx->v32(level + 1);
+  return residual_restrict<float>(ctx, level, static_cast<const float*>(p), static_cast<const float*>(f), nullptr,
+                                  static_cast<float*>(fc), nx.t);
+}
+
+int mg_prolong_add(mg_ctx* ctx, int prec, int level, const void* ec, void* p) {
+  MG_TRY(check_level(ctx, level, 1));
+  MG_TRY(check_prec(ctx, prec));
+  if (!ec || !p) return fail(MG_EINVAL, "null array pointer");
+  const Level& a = ctx->lv[level];
+  if (prec == MG_PREC_F64)
+    MG_HIP(mg::launch_prolong_add<double>(static_cast<const double*>(ec), static_cast<double*>(p), a.mask, a.q,
+                                          ctx->stream));
+  else
+    MG_HIP(mg::launch_prolong_add<float>(static_cast<const float*>(ec), static_cast<float*>(p), a.mask, a.q,
+                                         ctx->stream));
+  return MG_OK;
+}
+
+int mg_coarse_solve(mg_ctx* ctx, int prec, const void* f, void* e) {
+  if (!ctx) return fail(MG_EINVAL, "null context");
+  MG_TRY(check_prec(ctx, prec));
+  if (!f || !e) return fail(MG_EINVAL, "null array pointer");
+  const Level& a = ctx->lv[ctx->L - 1];
+  if (prec == MG_PREC_F64)
+    MG_HIP(mg::launch_coarse_solve<double>(static_cast<const double*>(f), static_cast<double*>(e), ctx->pinv, a.mask,
+                                           ctx->stream));
+  else
+    MG_HIP(mg::launch_coarse_solve<float>(static_cast<const float*>(f), static_cast<float*>(e), ctx->pinv, a.mask,
+                                          ctx->stream));
+  return MG_OK;
+}
+
+int mg_vcycle(mg_ctx* ctx, int prec, void* p, const void* f) {
+  if (!ctx) return fail(MG_EINVAL, "null context");
+  MG_TRY(check_prec(ctx, prec));
+  if (!p || !f) return fail(MG_EINVAL, "null array pointer");
+  if (prec == MG_PREC_F64) return vcycle<double>(ctx, 0, static_cast<double*>(p), static_cast<const double*>(f), nullptr);
+  return vcycle<float>(ctx, 0, static_cast<float*>(p), static_cast<const float*>(f), nullptr);
+}
+
+}  // extern "C"

@@ -1,0 +1,60 @@
+// Launchers of the device kernels (internal host API of the library).
+//
+// Arrays follow the layout of include/mg.h: [k][j][i] with x fastest, low-face
+// storage of the face coefficients.  `q` is log2 of the cells per side of the grid
+// a kernel works on.  Every launcher queues work on `s` and returns the launch status.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace mg {
+
+// ---- setup --------------------------------------------------------------------
+hipError_t launch_coeffs_from_rho(const double* rho, const uint8_t* mask, int q,
+                                  double* bx, double* by, double* bz, hipStream_t s);
+// counters[0] += non-finite or negative beta values, [1] += active cells, [2] += dropped
+hipError_t launch_setup_fine(const double* ubx, const double* uby, const double* ubz,
+                             const uint8_t* umask, int q, double* bx, double* by, double* bz,
+                             uint8_t* mask, long long* counters, hipStream_t s);
+hipError_t launch_coarsen(const double* bx, const double* by, const double* bz, const uint8_t* mask,
+                          int qc, double* cbx, double* cby, double* cbz, uint8_t* cmask, hipStream_t s);
+hipError_t launch_to_f32(const double* src, float* dst, long long count, hipStream_t s);
+
+// ---- V-cycle steps (T = double or float) ----------------------------------------
+// fshift: device scalar subtracted from f on active cells (nullptr = none)
+template <typename T>
+hipError_t launch_rbgs_half(T* p, const T* f, const T* bx, const T* by, const T* bz, int q,
+                            double h, int colour, const double* fshift, hipStream_t s);
+template <typename T>
+hipError_t launch_residual_restrict(const T* p, const T* f, const T* bx, const T* by, const T* bz,
+                                    int q, double h, const double* fshift, T* fc, T* ec_zero,
+                                    hipStream_t s);
+template <typename T>
+hipError_t launch_prolong_add(const T* ec, T* p, const uint8_t* mask, int q, hipStream_t s);
+template <typename T>
+hipError_t launch_coarse_solve(const T* f, T* e, const double* pinv, const uint8_t* mask, hipStream_t s);
+
+// ---- FP64 finest-grid passes ------------------------------------------------------
+// partials[blockIdx] = sum over active cells of r^2, r = (f - fshift) - A p; optional
+// r32 = float(r) and e32 = 0 (mixed-precision refinement); returns the block count used.
+hipError_t launch_residual_norm(const double* p, const double* f, const double* bx, const double* by,
+                                const double* bz, int q, double h, const double* fshift,
+                                float* r32, float* e32_zero, double* partials, int* nblocks,
+                                hipStream_t s);
+// mode 0: partials = sum_active x ; mode 1: sum_active (x - *shift)^2
+hipError_t launch_masked_sum(const double* x, const uint8_t* mask, int q, int mode, const double* shift,
+                             double* partials, int* nblocks, hipStream_t s);
+// out[0] = scale * sum(partials[0..nparts))  (single block, fixed order)
+hipError_t launch_reduce_final(const double* partials, int nparts, double scale, double* out, hipStream_t s);
+// p = mask ? p - *mean : 0   (mean may be nullptr: p = mask ? p : 0)
+hipError_t launch_gauge(double* p, const uint8_t* mask, int q, const double* mean, hipStream_t s);
+// p += mask ? double(e32) : 0
+hipError_t launch_update_p(double* p, const float* e32, const uint8_t* mask, int q, hipStream_t s);
+hipError_t launch_apply(const double* p, const double* bx, const double* by, const double* bz, int q,
+                        double h, double* Ap, hipStream_t s);
+hipError_t launch_coeff_grad(const double* mu, const double* p, int batch, const double* bx,
+                             const double* by, const double* bz, const uint8_t* mask, int q, double h,
+                             double* gbx, double* gby, double* gbz, double* grho, hipStream_t s);
+
+}  // namespace mg

@@ -1,0 +1,532 @@
+// Device kernels of the multigrid pressure solve for CDNA4 (gfx950).
+//
+// All kernels are memory-bound stencils on [k][j][i] arrays (x fastest) with
+// 32-bit cell indices (N <= 1024).  Conventions shared by every kernel:
+//   * periodic neighbours in x and y by masking with n-1 (n is a power of two);
+//   * z walls: the bottom-wall face bz[0] is zero after setup, and the top wall has no
+//     storage, so a z neighbour outside the grid is never read;
+//   * a cell is active exactly when its diagonal D = sum of its six face coefficients
+//     is positive: setup zeroes every face touching the body, and a coarse cell whose
+//     children are all body cells inherits only zero faces.  The V-cycle kernels use
+//     D > 0 instead of reading the mask.
+#include "mg_kernels.h"
+
+namespace mg {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ int cell(int i, int j, int k, int q) { return (((k << q) + j) << q) + i; }
+
+inline unsigned grid_for(long long work) {
+  return static_cast<unsigned>((work + kBlock - 1) / kBlock);
+}
+
+// Six face coefficients and the matching neighbour offsets of cell (i, j, k).
+template <typename T>
+struct Faces {
+  T xm, xp, ym, yp, zm, zp;   // beta on the low/high faces in x, y, z
+  int cxm, cxp, cym, cyp, czm, czp;
+};
+
+template <typename T>
+__device__ __forceinline__ Faces<T> load_faces(const T* __restrict__ bx, const T* __restrict__ by,
+                                               const T* __restrict__ bz, int i, int j, int k, int q) {
+  const int n = 1 << q, m = n - 1;
+  const int c = cell(i, j, k, q);
+  Faces<T> F;
+  F.cxm = cell((i - 1) & m, j, k, q);
+  F.cxp = cell((i + 1) & m, j, k, q);
+  F.cym = cell(i, (j - 1) & m, k, q);
+  F.cyp = cell(i, (j + 1) & m, k, q);
+  F.czm = k > 0 ? c - (1 << (2 * q)) : c;
+  F.czp = k < m ? c + (1 << (2 * q)) : c;
+  F.xm = bx[c];
+  F.xp = bx[F.cxp];
+  F.ym = by[c];
+  F.yp = by[F.cyp];
+  F.zm = bz[c];                          // 0 on the bottom wall
+  F.zp = k < m ? bz[F.czp] : T(0);       // top wall
+  return F;
+}
+
+template <typename T>
+__device__ __forceinline__ T diag(const Faces<T>& F) {
+  return F.xm + F.xp + F.ym + F.yp + F.zm + F.zp;
+}
+
+// sum_f beta_f (p_nb - p_c): the flux balance of A p without the h^-2 factor
+template <typename T>
+__device__ __forceinline__ T flux_sum(const Faces<T>& F, const T* __restrict__ p, T pc) {
+  return F.xm * (p[F.cxm] - pc) + F.xp * (p[F.cxp] - pc) + F.ym * (p[F.cym] - pc) +
+         F.yp * (p[F.cyp] - pc) + F.zm * (p[F.czm] - pc) + F.zp * (p[F.czp] - pc);
+}
+
+// ----------------------------------------------------------------------------- setup
+
+__global__ __launch_bounds__(kBlock) void k_coeffs_from_rho(const double* __restrict__ rho,
+                                                            const uint8_t* __restrict__ mask, int q,
+                                                            double* __restrict__ bx, double* __restrict__ by,
+                                                            double* __restrict__ bz) {
+  const int n = 1 << q, m = n - 1;
+  const long long t = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
+  if (t >= (1LL << (3 * q))) return;
+  const int c = static_cast<int>(t);
+  const int i = c & m, j = (c >> q) & m, k = c >> (2 * q);
+  const bool mc = mask[c] != 0;
+  const int cx = cell((i - 1) & m, j, k, q), cy = cell(i, (j - 1) & m, k, q);
+  bx[c] = (mc && mask[cx]) ? 2.0 / (rho[c] + rho[cx]) : 0.0;
+  by[c] = (mc && mask[cy]) ? 2.0 / (rho[c] + rho[cy]) : 0.0;
+  const int cz = c - (1 << (2 * q));
+  bz[c] = (k > 0 && mc && mask[cz]) ? 2.0 / (rho[c] + rho[cz]) : 0.0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_setup_fine(const double* __restrict__ ubx, const double* __restrict__ uby,
+                                                       const double* __restrict__ ubz,
+                                                       const uint8_t* __restrict__ umask, int q,
+                                                       double* __restrict__ bx, double* __restrict__ by,
+                                                       double* __restrict__ bz, uint8_t* __restrict__ mask,
+                                                       long long* __restrict__ counters) {
+  const int n = 1 << q, m = n - 1;
+  const long long t = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
+  const bool live = t < (1LL << (3 * q));
+  int bad = 0, active = 0, dropped = 0;
+  if (live) {
+    const int c = static_cast<int>(t);
+    const int i = c & m, j = (c >> q) & m, k = c >> (2 * q);
+    const bool mc = umask[c] != 0;
+    const int cxm = cell((i - 1) & m, j, k, q), cxp = cell((i + 1) & m, j, k, q);
+    const int cym = cell(i, (j - 1) & m, k, q), cyp = cell(i, (j + 1) & m, k, q);
+    const int nn = 1 << (2 * q);
+    const double vx = ubx[c], vy = uby[c], vz = ubz[c];
+    bad = !(vx >= 0.0 && vx <= 1.7976931348623157e308) + !(vy >= 0.0 && vy <= 1.7976931348623157e308) +
+          !(vz >= 0.0 && vz <= 1.7976931348623157e308);
+    const double xm = (mc && umask[cxm]) ? vx : 0.0;
+    const double ym = (mc && umask[cym]) ? vy : 0.0;
+    const double zm = (k > 0 && mc && umask[c - nn]) ? vz : 0.0;
+    const double xp = (mc && umask[cxp]) ? ubx[cxp] : 0.0;
+    const double yp = (mc && umask[cyp]) ? uby[cyp] : 0.0;
+    const double zp = (k < m && mc && umask[c + nn]) ? ubz[c + nn] : 0.0;
+    bx[c] = xm;
+    by[c] = ym;
+    bz[c] = zm;
+    const bool act = mc && (xm + xp + ym + yp + zm + zp) > 0.0;
+    mask[c] = act ? 1 : 0;
+    active = act;
+    dropped = mc && !act;
+  }
+  const int nb = __syncthreads_count(bad);
+  const int na = __syncthreads_count(active);
+  const int nd = __syncthreads_count(dropped);
+  if (threadIdx.x == 0) {
+    if (nb) atomicAdd(reinterpret_cast<unsigned long long*>(&counters[0]), static_cast<unsigned long long>(nb));
+    if (na) atomicAdd(reinterpret_cast<unsigned long long*>(&counters[1]), static_cast<unsigned long long>(na));
+    if (nd) atomicAdd(reinterpret_cast<unsigned long long*>(&counters[2]), static_cast<unsigned long long>(nd));
+  }
+}
+
+// Coarse face = mean of the 4 fine faces it covers; coarse cell active if any child is
+// active and it keeps an open face.  One thread per coarse cell.
+__global__ __launch_bounds__(kBlock) void k_coarsen(const double* __restrict__ bx, const double* __restrict__ by,
+                                                    const double* __restrict__ bz, const uint8_t* __restrict__ mask,
+                                                    int qc, double* __restrict__ cbx, double* __restrict__ cby,
+                                                    double* __restrict__ cbz, uint8_t* __restrict__ cmask) {
+  const int nc = 1 << qc, mc = nc - 1, q = qc + 1, mf = (1 << q) - 1;
+  const long long t = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
+  if (t >= (1LL << (3 * qc))) return;
+  const int C = static_cast<int>(t);
+  const int I = C & mc, J = (C >> qc) & mc, K = C >> (2 * qc);
+  const int i = 2 * I, j = 2 * J, k = 2 * K;
+  auto fx = [&](int ii) {   // x face at fine column ii (wrapped), 2 x 2 in (j, k)
+    ii &= mf;
+    return 0.25 * (bx[cell(ii, j, k, q)] + bx[cell(ii, j + 1, k, q)] + bx[cell(ii, j, k + 1, q)] +
+                   bx[cell(ii, j + 1, k + 1, q)]);
+  };
+  auto fy = [&](int jj) {
+    jj &= mf;
+    return 0.25 * (by[cell(i, jj, k, q)] + by[cell(i + 1, jj, k, q)] + by[cell(i, jj, k + 1, q)] +
+                   by[cell(i + 1, jj, k + 1, q)]);
+  };
+  auto fz = [&](int kk) {
+    return 0.25 * (bz[cell(i, j, kk, q)] + bz[cell(i + 1, j, kk, q)] + bz[cell(i, j + 1, kk, q)] +
+                   bz[cell(i + 1, j + 1, kk, q)]);
+  };
+  const double xm = fx(i), ym = fy(j), zm = fz(k);
+  const double xp = fx(i + 2), yp = fy(j + 2), zp = K < mc ? fz(k + 2) : 0.0;
+  cbx[C] = xm;
+  cby[C] = ym;
+  cbz[C] = zm;
+  bool any = false;
+  for (int d = 0; d < 8; ++d) any |= mask[cell(i + (d & 1), j + ((d >> 1) & 1), k + (d >> 2), q)] != 0;
+  cmask[C] = (any && (xm + xp + ym + yp + zm + zp) > 0.0) ? 1 : 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_to_f32(const double* __restrict__ src, float* __restrict__ dst,
+                                                   long long count) {
+  const long long t = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
+  if (t < count) dst[t] = static_cast<float>(src[t]);
+}
+
+// --------------------------------------------------------------------------- V-cycle
+
+// Gauss-Seidel on one colour, in place: each cell of that colour only reads cells of
+// the other colour, so the update order inside the launch does not matter.
+// One thread per pair of x-neighbours (one cell of each colour).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_rbgs_half(T* __restrict__ p, const T* __restrict__ f,
+                                                      const T* __restrict__ bx, const T* __restrict__ by,
+                                                      const T* __restrict__ bz, int q, T h2, int colour,
+                                                      const double* __restrict__ fshift) {
+  const int m = (1 << q) - 1;
+  const long long t = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
+  if (t >= (1LL << (3 * q - 1))) return;
+  const int pr = static_cast<int>(t);
+  const int ip = pr & (m >> 1), j = (pr >> (q - 1)) & m, k = pr >> (2 * q - 1);
+  const int i = 2 * ip + ((colour + j + k) & 1);
+  const Faces<T> F = load_faces(bx, by, bz, i, j, k, q);
+  const T D = diag(F);
+  if (!(D > T(0))) return;
+  const int c = cell(i, j, k, q);
+  const T fs = fshift ? static_cast<T>(*fshift) : T(0);
+  const T S = F.xm * p[F.cxm] + F.xp * p[F.cxp] + F.ym * p[F.cym] + F.yp * p[F.cyp] + F.zm * p[F.czm] +
+              F.zp * p[F.czp];
+  p[c] = (S - h2 * (f[c] - fs)) / D;
+}
+
+// fc = mean over the 8 children of r = (f - fshift) - A p; ec = 0.  One thread per coarse cell.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_residual_restrict(const T* __restrict__ p, const T* __restrict__ f,
+                                                              const T* __restrict__ bx, const T* __restrict__ by,
+                                                              const T* __restrict__ bz, int q, T inv_h2,
+                                                              const double* __restrict__ fshift,
+                                                              T* __restrict__ fc, T* __restrict__ ec) {
+  const int qc = q - 1, mc = (1 << qc) - 1;
+  const long long t = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
+  if (t >= (1LL << (3 * qc))) return;
+  const int C = static_cast<int>(t);
+  const int I = C & mc, J = (C >> qc) & mc, K = C >> (2 * qc);
+  const T fs = fshift ? static_cast<T>(*fshift) : T(0);
+  T sum = T(0);
+#pragma unroll
+  for (int d = 0; d < 8; ++d) {
+    const int i = 2 * I + (d & 1), j = 2 * J + ((d >> 1) & 1), k = 2 * K + (d >> 2);
+    const Faces<T> F = load_faces(bx, by, bz, i, j, k, q);
+    if (diag(F) > T(0)) {
+      const int c = cell(i, j, k, q);
+      sum += (f[c] - fs) - inv_h2 * flux_sum(F, p, p[c]);
+    }
+  }
+  fc[C] = sum * T(0.125);
+  ec[C] = T(0);
+}
+
+// p += mask * trilinear(ec); 1-D weights 3/4 (parent) and 1/4 (nearer neighbour),
+// periodic in x and y, parent reused for a z neighbour outside the grid.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_prolong_add(const T* __restrict__ ec, T* __restrict__ p,
+                                                        const uint8_t* __restrict__ mask, int q) {
+  const int m = (1 << q) - 1, qc = q - 1, mc = (1 << qc) - 1;
+  const long long t = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
+  if (t >= (1LL << (3 * q))) return;
+  const int c = static_cast<int>(t);
+  if (!mask[c]) return;
+  const int i = c & m, j = (c >> q) & m, k = c >> (2 * q);
+  const int I = i >> 1, J = j >> 1, K = k >> 1;
+  const int I2 = (I + ((i & 1) ? 1 : -1)) & mc;
+  const int J2 = (J + ((j & 1) ? 1 : -1)) & mc;
+  int K2 = K + ((k & 1) ? 1 : -1);
+  if (K2 < 0 || K2 > mc) K2 = K;
+  const T w3 = T(0.75), w1 = T(0.25);
+  auto row = [&](int jj, int kk) {   // x interpolation on coarse row (jj, kk)
+    return w3 * ec[cell(I, jj, kk, qc)] + w1 * ec[cell(I2, jj, kk, qc)];
+  };
+  const T lo = w3 * row(J, K) + w1 * row(J2, K);
+  const T hi = w3 * row(J, K2) + w1 * row(J2, K2);
+  p[c] += w3 * lo + w1 * hi;
+}
+
+// e = A_c^+ (f - active mean of f) on the 4^3 grid, in FP64; one wavefront of 64 lanes.
+template <typename T>
+__global__ __launch_bounds__(64) void k_coarse_solve(const T* __restrict__ f, T* __restrict__ e,
+                                                     const double* __restrict__ pinv,
+                                                     const uint8_t* __restrict__ mask) {
+  __shared__ double fh[64];
+  const int t = threadIdx.x;
+  const bool act = mask[t] != 0;
+  double v = act ? static_cast<double>(f[t]) : 0.0;
+  double s = v, cnt = act ? 1.0 : 0.0;
+  for (int off = 32; off > 0; off >>= 1) {
+    s += __shfl_xor(s, off, 64);
+    cnt += __shfl_xor(cnt, off, 64);
+  }
+  const double mean = cnt > 0.0 ? s / cnt : 0.0;
+  fh[t] = act ? v - mean : 0.0;
+  __syncthreads();
+  double acc = 0.0;
+  for (int c = 0; c < 64; ++c) acc += pinv[t * 64 + c] * fh[c];
+  e[t] = static_cast<T>(acc);
+}
+
+// ------------------------------------------------------------------ FP64 finest passes
+
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double red[kBlock / 64];
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < kBlock / 64; ++w) s += red[w];
+  return s;   // valid in thread 0
+}
+
+__global__ __launch_bounds__(kBlock) void k_residual_norm(const double* __restrict__ p, const double* __restrict__ f,
+                                                          const double* __restrict__ bx,
+                                                          const double* __restrict__ by,
+                                                          const double* __restrict__ bz, int q, double inv_h2,
+                                                          const double* __restrict__ fshift,
+                                                          float* __restrict__ r32, float* __restrict__ e32,
+                                                          double* __restrict__ partials) {
+  const int m = (1 << q) - 1;
+  const int total = 1 << (3 * q);
+  const double fs = fshift ? *fshift : 0.0;
+  double acc = 0.0;
+  for (int c = blockIdx.x * kBlock + threadIdx.x; c < total; c += gridDim.x * kBlock) {
+    const int i = c & m, j = (c >> q) & m, k = c >> (2 * q);
+    const Faces<double> F = load_faces(bx, by, bz, i, j, k, q);
+    double r = 0.0;
+    if (diag(F) > 0.0) r = (f[c] - fs) - inv_h2 * flux_sum(F, p, p[c]);
+    acc += r * r;
+    if (r32) {
+      r32[c] = static_cast<float>(r);
+      e32[c] = 0.0f;
+    }
+  }
+  const double s = block_sum(acc);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_masked_sum(const double* __restrict__ x, const uint8_t* __restrict__ mask,
+                                                       int total, int mode, const double* __restrict__ shift,
+                                                       double* __restrict__ partials) {
+  const double sh = (mode == 1 && shift) ? *shift : 0.0;
+  double acc = 0.0;
+  for (int c = blockIdx.x * kBlock + threadIdx.x; c < total; c += gridDim.x * kBlock) {
+    if (mask[c]) {
+      const double v = x[c] - sh;
+      acc += mode == 1 ? v * v : v;
+    }
+  }
+  const double s = block_sum(acc);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(1024) void k_reduce_final(const double* __restrict__ partials, int nparts,
+                                                       double scale, double* __restrict__ out) {
+  __shared__ double red[1024];
+  double s = 0.0;
+  for (int t = threadIdx.x; t < nparts; t += 1024) s += partials[t];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0] * scale;
+}
+
+__global__ __launch_bounds__(kBlock) void k_gauge(double* __restrict__ p, const uint8_t* __restrict__ mask, int total,
+                                                  const double* __restrict__ mean) {
+  const long long t = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
+  if (t >= total) return;
+  const double mu = mean ? *mean : 0.0;
+  p[t] = mask[t] ? p[t] - mu : 0.0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_update_p(double* __restrict__ p, const float* __restrict__ e32,
+                                                     const uint8_t* __restrict__ mask, int total) {
+  const long long t = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
+  if (t >= total) return;
+  if (mask[t]) p[t] += static_cast<double>(e32[t]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_apply(const double* __restrict__ p, const double* __restrict__ bx,
+                                                  const double* __restrict__ by, const double* __restrict__ bz,
+                                                  int q, double inv_h2, double* __restrict__ Ap) {
+  const int m = (1 << q) - 1;
+  const long long t = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
+  if (t >= (1LL << (3 * q))) return;
+  const int c = static_cast<int>(t);
+  const Faces<double> F = load_faces(bx, by, bz, c & m, (c >> q) & m, c >> (2 * q), q);
+  Ap[c] = inv_h2 * flux_sum(F, p, p[c]);
+}
+
+// dL/dbeta on the low faces of each cell and dL/drho_c = -1/2 sum_f beta_f^2 dL/dbeta_f;
+// high faces are recomputed from the neighbours so no thread waits on another.
+__global__ __launch_bounds__(kBlock) void k_coeff_grad(const double* __restrict__ mu, const double* __restrict__ p,
+                                                       int batch, const double* __restrict__ bx,
+                                                       const double* __restrict__ by,
+                                                       const double* __restrict__ bz,
+                                                       const uint8_t* __restrict__ mask, int q, double inv_h2,
+                                                       double* __restrict__ gbx, double* __restrict__ gby,
+                                                       double* __restrict__ gbz, double* __restrict__ grho) {
+  const int m = (1 << q) - 1;
+  const long long total = 1LL << (3 * q);
+  const long long t = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
+  if (t >= total) return;
+  const int c = static_cast<int>(t);
+  const int i = c & m, j = (c >> q) & m, k = c >> (2 * q);
+  const int nb[6] = {cell((i - 1) & m, j, k, q), cell((i + 1) & m, j, k, q), cell(i, (j - 1) & m, k, q),
+                     cell(i, (j + 1) & m, k, q), k > 0 ? c - (1 << (2 * q)) : c,
+                     k < m ? c + (1 << (2 * q)) : c};
+  const bool mc = mask[c] != 0;
+  bool open[6];
+  for (int f = 0; f < 6; ++f) open[f] = mc && mask[nb[f]] != 0;
+  open[4] = open[4] && k > 0;
+  open[5] = open[5] && k < m;
+  double g[6] = {0, 0, 0, 0, 0, 0};
+  for (int b = 0; b < batch; ++b) {
+    const double* mb = mu + static_cast<long long>(b) * total;
+    const double* pb = p + static_cast<long long>(b) * total;
+    const double mcv = mb[c], pcv = pb[c];
+    for (int f = 0; f < 6; ++f)
+      if (open[f]) g[f] += (mb[nb[f]] - mcv) * (pb[nb[f]] - pcv);
+  }
+  for (int f = 0; f < 6; ++f) g[f] *= inv_h2;
+  if (gbx) gbx[c] = g[0];
+  if (gby) gby[c] = g[2];
+  if (gbz) gbz[c] = g[4];
+  if (grho) {
+    const double b[6] = {bx[c], bx[nb[1]], by[c], by[nb[3]], bz[c], k < m ? bz[nb[5]] : 0.0};
+    double s = 0.0;
+    for (int f = 0; f < 6; ++f) s += b[f] * b[f] * g[f];
+    grho[c] = -0.5 * s;
+  }
+}
+
+int reduction_blocks(long long total) {
+  long long b = (total + kBlock - 1) / kBlock;
+  return static_cast<int>(b < 2048 ? b : 2048);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------- launchers
+
+hipError_t launch_coeffs_from_rho(const double* rho, const uint8_t* mask, int q, double* bx, double* by,
+                                  double* bz, hipStream_t s) {
+  hipLaunchKernelGGL(k_coeffs_from_rho, dim3(grid_for(1LL << (3 * q))), dim3(kBlock), 0, s, rho, mask, q, bx, by, bz);
+  return hipGetLastError();
+}
+
+hipError_t launch_setup_fine(const double* ubx, const double* uby, const double* ubz, const uint8_t* umask, int q,
+                             double* bx, double* by, double* bz, uint8_t* mask, long long* counters,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_setup_fine, dim3(grid_for(1LL << (3 * q))), dim3(kBlock), 0, s, ubx, uby, ubz, umask, q, bx,
+                     by, bz, mask, counters);
+  return hipGetLastError();
+}
+
+hipError_t launch_coarsen(const double* bx, const double* by, const double* bz, const uint8_t* mask, int qc,
+                          double* cbx, double* cby, double* cbz, uint8_t* cmask, hipStream_t s) {
+  hipLaunchKernelGGL(k_coarsen, dim3(grid_for(1LL << (3 * qc))), dim3(kBlock), 0, s, bx, by, bz, mask, qc, cbx, cby,
+                     cbz, cmask);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_f32(const double* src, float* dst, long long count, hipStream_t s) {
+  hipLaunchKernelGGL(k_to_f32, dim3(grid_for(count)), dim3(kBlock), 0, s, src, dst, count);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_rbgs_half(T* p, const T* f, const T* bx, const T* by, const T* bz, int q, double h, int colour,
+                            const double* fshift, hipStream_t s) {
+  const T h2 = static_cast<T>(h * h);
+  hipLaunchKernelGGL(k_rbgs_half<T>, dim3(grid_for(1LL << (3 * q - 1))), dim3(kBlock), 0, s, p, f, bx, by, bz, q,
+                     h2, colour, fshift);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_residual_restrict(const T* p, const T* f, const T* bx, const T* by, const T* bz, int q, double h,
+                                    const double* fshift, T* fc, T* ec, hipStream_t s) {
+  const T inv_h2 = static_cast<T>(1.0 / (h * h));
+  hipLaunchKernelGGL(k_residual_restrict<T>, dim3(grid_for(1LL << (3 * (q - 1)))), dim3(kBlock), 0, s, p, f, bx, by,
+                     bz, q, inv_h2, fshift, fc, ec);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_prolong_add(const T* ec, T* p, const uint8_t* mask, int q, hipStream_t s) {
+  hipLaunchKernelGGL(k_prolong_add<T>, dim3(grid_for(1LL << (3 * q))), dim3(kBlock), 0, s, ec, p, mask, q);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_coarse_solve(const T* f, T* e, const double* pinv, const uint8_t* mask, hipStream_t s) {
+  hipLaunchKernelGGL(k_coarse_solve<T>, dim3(1), dim3(64), 0, s, f, e, pinv, mask);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual_norm(const double* p, const double* f, const double* bx, const double* by,
+                                const double* bz, int q, double h, const double* fshift, float* r32,
+                                float* e32, double* partials, int* nblocks, hipStream_t s) {
+  const int nb = reduction_blocks(1LL << (3 * q));
+  hipLaunchKernelGGL(k_residual_norm, dim3(nb), dim3(kBlock), 0, s, p, f, bx, by, bz, q, 1.0 / (h * h), fshift, r32,
+                     e32, partials);
+  *nblocks = nb;
+  return hipGetLastError();
+}
+
+hipError_t launch_masked_sum(const double* x, const uint8_t* mask, int q, int mode, const double* shift,
+                             double* partials, int* nblocks, hipStream_t s) {
+  const int nb = reduction_blocks(1LL << (3 * q));
+  hipLaunchKernelGGL(k_masked_sum, dim3(nb), dim3(kBlock), 0, s, x, mask, 1 << (3 * q), mode, shift, partials);
+  *nblocks = nb;
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_final(const double* partials, int nparts, double scale, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(1024), 0, s, partials, nparts, scale, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_gauge(double* p, const uint8_t* mask, int q, const double* mean, hipStream_t s) {
+  hipLaunchKernelGGL(k_gauge, dim3(grid_for(1LL << (3 * q))), dim3(kBlock), 0, s, p, mask, 1 << (3 * q), mean);
+  return hipGetLastError();
+}
+
+hipError_t launch_update_p(double* p, const float* e32, const uint8_t* mask, int q, hipStream_t s) {
+  hipLaunchKernelGGL(k_update_p, dim3(grid_for(1LL << (3 * q))), dim3(kBlock), 0, s, p, e32, mask, 1 << (3 * q));
+  return hipGetLastError();
+}
+
+hipError_t launch_apply(const double* p, const double* bx, const double* by, const double* bz, int q, double h,
+                        double* Ap, hipStream_t s) {
+  hipLaunchKernelGGL(k_apply, dim3(grid_for(1LL << (3 * q))), dim3(kBlock), 0, s, p, bx, by, bz, q, 1.0 / (h * h), Ap);
+  return hipGetLastError();
+}
+
+hipError_t launch_coeff_grad(const double* mu, const double* p, int batch, const double* bx, const double* by,
+                             const double* bz, const uint8_t* mask, int q, double h, double* gbx, double* gby,
+                             double* gbz, double* grho, hipStream_t s) {
+  hipLaunchKernelGGL(k_coeff_grad, dim3(grid_for(1LL << (3 * q))), dim3(kBlock), 0, s, mu, p, batch, bx, by, bz, mask,
+                     q, 1.0 / (h * h), gbx, gby, gbz, grho);
+  return hipGetLastError();
+}
+
+#define MG_INSTANTIATE(T)                                                                                        \
+  template hipError_t launch_rbgs_half<T>(T*, const T*, const T*, const T*, const T*, int, double, int,          \
+                                          const double*, hipStream_t);                                           \
+  template hipError_t launch_residual_restrict<T>(const T*, const T*, const T*, const T*, const T*, int, double, \
+                                                  const double*, T*, T*, hipStream_t);                           \
+  template hipError_t launch_prolong_add<T>(const T*, T*, const uint8_t*, int, hipStream_t);                     \
+  template hipError_t launch_coarse_solve<T>(const T*, T*, const double*, const uint8_t*, hipStream_t);
+MG_INSTANTIATE(double)
+MG_INSTANTIATE(float)
+#undef MG_INSTANTIATE
+
+}  // namespace mg

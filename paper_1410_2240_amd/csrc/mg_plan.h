@@ -1,0 +1,54 @@
+// Level plan and workspace layout of the multigrid solver (pure host C++).
+//
+// Every grid of the hierarchy halves the cell count per side of the one above it,
+// from the finest N down to the 4^3 grid that is solved directly (section 3.1 keeps
+// the face products on every grid, so each level stores its own three face arrays).
+// This file only does arithmetic on sizes and offsets; it is compiled into the HIP
+// library and, unchanged, into a host-only test program.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+
+namespace mg {
+
+constexpr int kCoarsest = 4;          // cells per side of the directly solved grid
+constexpr int kMaxN = 1024;           // N^3 < 2^31: 32-bit cell indices throughout
+constexpr int kMaxLevels = 10;        // 1024 -> 4
+constexpr int kNumPartials = 2048;    // blocks of the two-pass reductions
+constexpr size_t kAlign = 256;
+
+struct LevelPlan {
+  int n = 0;         // cells per side
+  int log2n = 0;
+  // FP64 arrays (byte offsets into the workspace; SIZE_MAX = absent)
+  size_t bx = 0, by = 0, bz = 0;   // face coefficients
+  size_t mask = 0;                 // uint8 activity
+  size_t f = 0, e = 0;             // right-hand side / correction (levels >= 1)
+  size_t t = 0;                    // second buffer for out-of-place sweeps
+  // FP32 arrays (mixed precision only)
+  size_t bx32 = 0, by32 = 0, bz32 = 0;
+  size_t f32 = 0, e32 = 0, t32 = 0;
+};
+
+struct Plan {
+  int n = 0;
+  int levels = 0;
+  int flags = 0;
+  LevelPlan lv[kMaxLevels];
+  size_t pinv = 0;       // (4^3)^2 doubles: pseudo-inverse of the coarsest operator
+  size_t partials = 0;   // kNumPartials doubles
+  size_t scalars = 0;    // 32 doubles of device scalars
+  size_t counters = 0;   // 16 int64 counters (setup validation and counts)
+  size_t total = 0;      // bytes
+};
+
+constexpr size_t kAbsent = static_cast<size_t>(-1);
+
+// 0 if dims describe a supported cube (equal powers of two, 8..1024), else -1.
+int validate_dims(const int dims[3], int* n_out);
+
+// Fills `plan` for an N^3 grid; returns 0, or -1 for unsupported N or flags.
+int build_plan(int n, int flags, Plan* plan);
+
+}  // namespace mg

@@ -1,0 +1,102 @@
+// Host-only checks of the level plan and workspace layout (built with g++, no GPU).
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+
+#include "mg_plan.h"
+
+namespace mg {
+void symmetric_pinv(int n, std::vector<double>& a, double rtol, std::vector<double>& pinv);
+}
+
+static int failures = 0;
+#define CHECK(c)                                                   \
+  do {                                                             \
+    if (!(c)) {                                                    \
+      std::printf("FAIL %s:%d: %s\n", __FILE__, __LINE__, #c);     \
+      ++failures;                                                  \
+    }                                                              \
+  } while (0)
+
+struct Span {
+  size_t off, len;
+};
+
+static void check_layout(int n, int flags) {
+  mg::Plan p;
+  CHECK(mg::build_plan(n, flags, &p) == 0);
+  int L = 0;
+  for (int m = n; m >= 4; m /= 2) ++L;
+  CHECK(p.levels == L);
+  CHECK(p.lv[L - 1].n == 4);
+  std::vector<Span> spans;
+  for (int l = 0; l < p.levels; ++l) {
+    const mg::LevelPlan& a = p.lv[l];
+    CHECK(a.n == (n >> l));
+    CHECK((1 << a.log2n) == a.n);
+    const size_t c = static_cast<size_t>(a.n) * a.n * a.n;
+    spans.push_back({a.bx, c * 8});
+    spans.push_back({a.by, c * 8});
+    spans.push_back({a.bz, c * 8});
+    spans.push_back({a.mask, c});
+    spans.push_back({a.t, c * 8});
+    if (l > 0) {
+      spans.push_back({a.f, c * 8});
+      spans.push_back({a.e, c * 8});
+    } else {
+      CHECK(a.f == mg::kAbsent && a.e == mg::kAbsent);
+    }
+    if (flags == 1) {
+      for (size_t o : {a.bx32, a.by32, a.bz32, a.f32, a.e32, a.t32}) spans.push_back({o, c * 4});
+    } else {
+      CHECK(a.bx32 == mg::kAbsent && a.f32 == mg::kAbsent);
+    }
+  }
+  spans.push_back({p.pinv, 64 * 64 * 8});
+  spans.push_back({p.partials, mg::kNumPartials * 8});
+  spans.push_back({p.scalars, 32 * 8});
+  spans.push_back({p.counters, 16 * 8});
+  for (size_t i = 0; i < spans.size(); ++i) {
+    CHECK(spans[i].off % mg::kAlign == 0);
+    CHECK(spans[i].off + spans[i].len <= p.total);
+    for (size_t j = i + 1; j < spans.size(); ++j) {
+      const bool disjoint = spans[i].off + spans[i].len <= spans[j].off || spans[j].off + spans[j].len <= spans[i].off;
+      CHECK(disjoint);
+    }
+  }
+}
+
+int main() {
+  const int good[3] = {64, 64, 64};
+  int n = 0;
+  CHECK(mg::validate_dims(good, &n) == 0 && n == 64);
+  const int bad[][3] = {{64, 64, 32}, {48, 48, 48}, {4, 4, 4}, {2048, 2048, 2048}, {0, 0, 0}, {-8, -8, -8}};
+  for (const auto& d : bad) CHECK(mg::validate_dims(d, nullptr) != 0);
+  CHECK(mg::validate_dims(nullptr, nullptr) != 0);
+  mg::Plan p;
+  CHECK(mg::build_plan(64, 2, &p) != 0);
+  for (int m : {8, 16, 64, 256})
+    for (int fl : {0, 1}) check_layout(m, fl);
+  // 1024^3 FP64: three FP64 face arrays, the mask and the second buffer on the finest grid
+  CHECK(mg::build_plan(1024, 0, &p) == 0);
+  const double fine = 1024.0 * 1024 * 1024 * (3 * 8 + 1 + 8);
+  // coarse grids add 1/7 of that plus their right-hand side and correction
+  CHECK(p.total > fine && p.total < 1024.0 * 1024 * 1024 * 41);
+  // pseudo-inverse of a symmetric singular matrix: A A+ A = A
+  std::vector<double> a = {2, -1, -1, -1, 2, -1, -1, -1, 2}, pinv;
+  std::vector<double> a0 = a;
+  mg::symmetric_pinv(3, a, 1e-12, pinv);
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      double s = 0;
+      for (int k = 0; k < 3; ++k)
+        for (int l = 0; l < 3; ++l) s += a0[r * 3 + k] * pinv[k * 3 + l] * a0[l * 3 + c];
+      CHECK(std::abs(s - a0[r * 3 + c]) < 1e-12);
+    }
+  // pinv of diag(2, 4) with a zero eigenvalue block
+  std::vector<double> d = {2, 0, 0, 0, 4, 0, 0, 0, 0};
+  mg::symmetric_pinv(3, d, 1e-12, pinv);
+  CHECK(std::abs(pinv[0] - 0.5) < 1e-15 && std::abs(pinv[4] - 0.25) < 1e-15 && pinv[8] == 0.0);
+  std::printf("%s (%d failures)\n", failures ? "FAILED" : "OK", failures);
+  return failures ? 1 : 0;
+}

@@ -1,0 +1,172 @@
+"""Solve parity: GPU solutions against the oracle's exact solutions and multigrid.
+
+Bar: relative L2 error on p <= 1e-9 (FP64, and mixed precision after convergence).
+Parity runs solve to 1e-12 so that the error bound (condition number x residual)
+sits well below the bar; the bench workloads at full size are checked through the
+oracle's own residual of the GPU solution, which holds at any size.
+"""
+import numpy as np
+import pytest
+import torch
+
+import fields
+from oracle import exact
+from oracle import multigrid as omg
+from oracle.operator import apply as oapply
+from oracle.operator import project
+from tests.gpu_helpers import dev, host, mg_from_inputs, relerr, workload
+
+pytestmark = pytest.mark.gpu
+
+
+def oracle_relres(inp, H, p):
+    fh = project(inp.f, H.fine.mask)
+    r = np.where(H.fine.mask, fh - oapply(p, H.fine), 0.0)
+    return float(np.linalg.norm(r) / np.linalg.norm(fh))
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_flat_32_matches_fft_exact(mixed):
+    inp, H = workload("c1", 32)
+    mg = mg_from_inputs(inp, mixed)
+    p, hist, st = mg.solve(dev(inp.f), tol=1e-12, max_cycles=60)
+    pe = exact.solve_fft_z(H.fine, inp.f)
+    assert relerr(host(p), pe) <= 1e-9
+    assert hist[-1] <= 1e-12 and st["status"] == 0
+    # FP64 history follows the oracle's multigrid cycle by cycle
+    if not mixed:
+        _, ohist = omg.solve(H, inp.f, tol=1e-12, max_cycles=60)
+        assert len(hist) == len(ohist)
+        for a, b in zip(hist, ohist):
+            # cycle-by-cycle agreement down to the rounding floor of the residual norm
+            assert abs(a - b) <= 1e-6 * b + 1e-15
+
+
+def test_dense_cross_check_8():
+    inp, H = workload("c1", 8)
+    mg = mg_from_inputs(inp)
+    p, hist, _ = mg.solve(dev(inp.f), tol=1e-13, max_cycles=80)
+    assert relerr(host(p), exact.solve_dense(H.fine, inp.f)) <= 1e-9
+
+
+def test_constant_density_eigenfunction():
+    """rho = 1 everywhere: f = lambda * cos mode (a,b,c) = (1,2,3) gives p = that mode."""
+    N = 32
+    c = (np.arange(N) + 0.5) / N
+    z, y, x = np.meshgrid(c, c, c, indexing="ij")
+    mode = np.cos(2 * np.pi * x) * np.cos(4 * np.pi * y) * np.cos(3 * np.pi * z)
+    lam = -(4.0 * N * N) * (np.sin(np.pi / N) ** 2 + np.sin(2 * np.pi / N) ** 2 + np.sin(3 * np.pi / (2 * N)) ** 2)
+    rho = np.ones((N, N, N))
+    mask = np.ones((N, N, N), np.uint8)
+    from paper_1410_2240_amd import MG
+    mg = MG.from_rho(dev(rho), dev(mask))
+    p, _, _ = mg.solve(dev(lam * mode), tol=1e-13, max_cycles=60)
+    assert relerr(host(p), mode) <= 1e-9
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_wavy_body_32_matches_sparse_direct(mixed):
+    inp, H = workload("c2", 32)
+    mg = mg_from_inputs(inp, mixed)
+    p, hist, st = mg.solve(dev(inp.f), tol=1e-12, max_cycles=100)
+    pe = exact.solve_sparse(H.fine, inp.f)
+    got = host(p)
+    assert relerr(got, pe) <= 1e-9
+    assert np.all(got[inp.mask == 0] == 0)
+    assert abs(got[inp.mask == 1].mean()) <= 1e-12 * np.abs(got).max()
+
+
+@pytest.mark.parametrize("name,N", [("c2", 64), ("c5", 64), ("c3", 64)])
+def test_workloads_64_match_oracle_multigrid(name, N):
+    inp, H = workload(name, N)
+    want, _ = omg.solve(H, inp.f, tol=1e-12, max_cycles=100)
+    for mixed in (False, True):
+        mg = mg_from_inputs(inp, mixed)
+        p, hist, _ = mg.solve(dev(inp.f), tol=1e-12, max_cycles=100)
+        assert relerr(host(p), want) <= 1e-9, (name, mixed)
+
+
+def test_flat_128_mixed_matches_fft():
+    inp, H = workload("c3", 128)
+    pe = exact.solve_fft_z(H.fine, inp.f)
+    for mixed in (False, True):
+        p, hist, st = mg_from_inputs(inp, mixed).solve(dev(inp.f), tol=1e-12, max_cycles=100)
+        assert relerr(host(p), pe) <= 1e-9, mixed
+
+
+def test_bench_workload_256_residual_by_oracle():
+    """The benchmarked 256^3 wavy-interface + body workload, solved as the benchmark
+    does (FP64 and mixed, tol 1e-10): the oracle recomputes the residual in FP64."""
+    inp, H = workload("c2", 256)
+    for mixed in (False, True):
+        p, hist, st = mg_from_inputs(inp, mixed).solve(dev(inp.f), tol=1e-10, max_cycles=100)
+        rr = oracle_relres(inp, H, host(p))
+        assert rr <= 1.05e-10, (mixed, rr, hist[-3:])
+        assert abs(rr - hist[-1]) <= 1e-3 * hist[-1] + 1e-14
+
+
+def test_repeatable_bitwise():
+    inp, _ = workload("c2", 32)
+    mg = mg_from_inputs(inp)
+    a, ha, _ = mg.solve(dev(inp.f), tol=1e-12)
+    b, hb, _ = mg.solve(dev(inp.f), tol=1e-12)
+    assert torch.equal(a, b) and ha == hb
+
+
+def test_batch_and_warm_start():
+    inp, H = workload("c1", 32)
+    mg = mg_from_inputs(inp)
+    fb = fields.batch_rhs(inp.mask, 3)
+    p, hists, st = mg.solve(dev(fb), tol=1e-12)
+    for b in range(3):
+        assert relerr(host(p[b]), exact.solve_fft_z(H.fine, fb[b])) <= 1e-9
+    assert len(hists) == 3 and st["cycles"] == sum(len(h) - 1 for h in hists)
+    p2, h2, _ = mg.solve(dev(fb[0]), p=p[0].clone(), tol=1e-12)
+    assert len(h2) == 1   # already converged
+
+
+# ------------------------------------------------------------------ error paths
+
+def test_errors_reported():
+    from paper_1410_2240_amd import MG, MGError
+    from paper_1410_2240_amd._lib import MG_EBREAKDOWN, MG_EINVAL, MG_ENOCONV
+    inp, H = workload("c1", 16)
+    mg = mg_from_inputs(inp)
+    p, hist, st = mg.solve(dev(inp.f), tol=1e-12, max_cycles=1, raise_on_fail=False)
+    assert st["status"] == MG_ENOCONV and len(hist) == 2
+    bad = inp.f.copy()
+    bad[3, 3, 3] = np.nan
+    _, _, st = mg.solve(dev(bad), raise_on_fail=False)
+    assert st["status"] == MG_EBREAKDOWN
+    with pytest.raises(MGError) as ei:
+        mg.solve(dev(inp.f), tol=-1.0)
+    assert ei.value.code == MG_EINVAL
+    neg = np.ones((16, 16, 16))
+    neg[1, 2, 3] = -1.0
+    with pytest.raises(MGError):
+        MG(dev(neg), dev(np.ones((16,) * 3)), dev(np.ones((16,) * 3)), dev(np.ones((16,) * 3, np.uint8)))
+    with pytest.raises(ValueError):
+        MG(dev(np.ones((12,) * 3)), dev(np.ones((12,) * 3)), dev(np.ones((12,) * 3)), dev(np.ones((12,) * 3, np.uint8)))
+
+
+def test_incompatible_rhs_mean_removed():
+    inp, H = workload("c2", 32)
+    mg = mg_from_inputs(inp)
+    shifted = np.where(inp.mask == 1, inp.f + 7.5, 0.0)
+    p, hist, st = mg.solve(dev(shifted), tol=1e-12)
+    assert st["removed_mean"] == pytest.approx(7.5, rel=1e-9)
+    assert relerr(host(p), exact.solve_sparse(H.fine, inp.f)) <= 1e-9
+
+
+def test_isolated_fluid_cell_dropped():
+    """A fluid cell enclosed by body cells has no equation: it is reported and kept at 0."""
+    from paper_1410_2240_amd import MG
+    N = 16
+    rho = np.ones((N, N, N))
+    mask = np.ones((N, N, N), np.uint8)
+    mask[4:9, 4:9, 4:9] = 0
+    mask[6, 6, 6] = 1
+    mg = MG.from_rho(dev(rho), dev(mask))
+    f = fields.divergence_rhs(mask)
+    p, hist, st = mg.solve(dev(f), tol=1e-12)
+    assert st["dropped_cells"] == 1 and host(p)[6, 6, 6] == 0.0
