@@ -111,10 +111,25 @@ long long cells(const Level& a) { return static_cast<long long>(a.n) * a.n * a.n
 
 // ---------------------------------------------------------------- V-cycle (T = double/float)
 
+// `sweeps` red-black sweeps of A p = f on level l.  Large grids use the one-pass fused
+// sweep, which alternates p with the level's second buffer; an odd count ends with a
+// copy back.  Small grids use two in-place half-sweeps per sweep.
 template <typename T>
 int smooth(mg_ctx* c, int l, T* p, const T* f, const double* fshift, int sweeps, int order) {
   const Level& a = c->lv[l];
   const View<T> v = c->view<T>(l);
+  if (mg::fused_sweep_supported(a.q)) {
+    T* src = p;
+    T* dst = v.t;
+    for (int s = 0; s < sweeps; ++s) {
+      MG_HIP(mg::launch_rbgs_fused<T>(src, dst, f, v.bx, v.by, v.bz, a.q, a.h, order, fshift, c->stream));
+      T* tmp = src;
+      src = dst;
+      dst = tmp;
+    }
+    if (src != p) MG_HIP(hipMemcpyAsync(p, src, sizeof(T) * cells(a), hipMemcpyDeviceToDevice, c->stream));
+    return MG_OK;
+  }
   for (int s = 0; s < sweeps; ++s) {
     for (int half = 0; half < 2; ++half) {
       const int colour = (order == MG_PRE) ? half : 1 - half;   // red = 0 first when pre-smoothing

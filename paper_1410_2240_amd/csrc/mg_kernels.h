@@ -26,6 +26,12 @@ hipError_t launch_to_f32(const double* src, float* dst, long long count, hipStre
 template <typename T>
 hipError_t launch_rbgs_half(T* p, const T* f, const T* bx, const T* by, const T* bz, int q,
                             double h, int colour, const double* fshift, hipStream_t s);
+// One full red-black sweep in one pass, out of place (pin -> pout, distinct buffers);
+// order 0 = red then black, 1 = black then red.  Grids with at least 64 cells per side.
+int fused_sweep_supported(int q);
+template <typename T>
+hipError_t launch_rbgs_fused(const T* pin, T* pout, const T* f, const T* bx, const T* by, const T* bz, int q,
+                             double h, int order, const double* fshift, hipStream_t s);
 template <typename T>
 hipError_t launch_residual_restrict(const T* p, const T* f, const T* bx, const T* by, const T* bz,
                                     int q, double h, const double* fshift, T* fc, T* ec_zero,

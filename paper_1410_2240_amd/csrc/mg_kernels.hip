@@ -10,6 +10,7 @@
 //     children are all body cells inherits only zero faces.  The V-cycle kernels use
 //     D > 0 instead of reading the mask.
 #include "mg_kernels.h"
+#include "mg_plan.h"
 
 namespace mg {
 
@@ -61,6 +62,54 @@ template <typename T>
 __device__ __forceinline__ T flux_sum(const Faces<T>& F, const T* __restrict__ p, T pc) {
   return F.xm * (p[F.cxm] - pc) + F.xp * (p[F.cxp] - pc) + F.ym * (p[F.cym] - pc) +
          F.yp * (p[F.cyp] - pc) + F.zm * (p[F.czm] - pc) + F.zp * (p[F.czp] - pc);
+}
+
+template <typename T>
+struct V2of;
+template <>
+struct V2of<double> {
+  using type = double2;
+};
+template <>
+struct V2of<float> {
+  using type = float2;
+};
+
+template <typename T>
+__device__ __forceinline__ typename V2of<T>::type ld2(const T* __restrict__ a, int c) {
+  return *reinterpret_cast<const typename V2of<T>::type*>(a + c);
+}
+
+// Residuals r = (f - fs) - h^-2 sum_f beta_f (p_nb - p_c) of the x-neighbour pair
+// (i, j, k), (i+1, j, k) with i even, 0 on inactive cells.  All loads but the two
+// outer x neighbours are 2-wide and contiguous across adjacent threads.
+template <typename T>
+__device__ __forceinline__ void pair_residual(const T* __restrict__ p, const T* __restrict__ f,
+                                              const T* __restrict__ bx, const T* __restrict__ by,
+                                              const T* __restrict__ bz, int i, int j, int k, int q, T inv_h2, T fs,
+                                              T& r0, T& r1) {
+  using V2 = typename V2of<T>::type;
+  const int m = (1 << q) - 1, nn = 1 << (2 * q);
+  const int c = cell(i, j, k, q);
+  const V2 pc = ld2(p, c);
+  const T pl = p[cell((i - 1) & m, j, k, q)], pr = p[cell((i + 2) & m, j, k, q)];
+  const V2 pyd = ld2(p, cell(i, (j - 1) & m, k, q)), pyu = ld2(p, cell(i, (j + 1) & m, k, q));
+  const V2 pzd = k > 0 ? ld2(p, c - nn) : pc;
+  const V2 pzu = k < m ? ld2(p, c + nn) : pc;
+  const V2 fv = ld2(f, c);
+  const V2 bxv = ld2(bx, c);
+  const T bxr = bx[cell((i + 2) & m, j, k, q)];
+  const V2 byv = ld2(by, c), byu = ld2(by, cell(i, (j + 1) & m, k, q));
+  const V2 bzv = ld2(bz, c);
+  const V2 bzu = k < m ? ld2(bz, c + nn) : V2{T(0), T(0)};
+  const T D0 = bxv.x + bxv.y + byv.x + byu.x + bzv.x + bzu.x;
+  const T D1 = bxv.y + bxr + byv.y + byu.y + bzv.y + bzu.y;
+  const T s0 = bxv.x * (pl - pc.x) + bxv.y * (pc.y - pc.x) + byv.x * (pyd.x - pc.x) + byu.x * (pyu.x - pc.x) +
+               bzv.x * (pzd.x - pc.x) + bzu.x * (pzu.x - pc.x);
+  const T s1 = bxv.y * (pc.x - pc.y) + bxr * (pr - pc.y) + byv.y * (pyd.y - pc.y) + byu.y * (pyu.y - pc.y) +
+               bzv.y * (pzd.y - pc.y) + bzu.y * (pzu.y - pc.y);
+  r0 = D0 > T(0) ? (fv.x - fs) - inv_h2 * s0 : T(0);
+  r1 = D1 > T(0) ? (fv.y - fs) - inv_h2 * s1 : T(0);
 }
 
 // ----------------------------------------------------------------------------- setup
@@ -194,7 +243,8 @@ __global__ __launch_bounds__(kBlock) void k_rbgs_half(T* __restrict__ p, const T
   p[c] = (S - h2 * (f[c] - fs)) / D;
 }
 
-// fc = mean over the 8 children of r = (f - fshift) - A p; ec = 0.  One thread per coarse cell.
+// fc = mean over the 8 children of r = (f - fshift) - A p; ec = 0.  One thread per
+// coarse cell: its children are two x-pairs on each of two rows and two planes.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_residual_restrict(const T* __restrict__ p, const T* __restrict__ f,
                                                               const T* __restrict__ bx, const T* __restrict__ by,
@@ -209,41 +259,64 @@ __global__ __launch_bounds__(kBlock) void k_residual_restrict(const T* __restric
   const T fs = fshift ? static_cast<T>(*fshift) : T(0);
   T sum = T(0);
 #pragma unroll
-  for (int d = 0; d < 8; ++d) {
-    const int i = 2 * I + (d & 1), j = 2 * J + ((d >> 1) & 1), k = 2 * K + (d >> 2);
-    const Faces<T> F = load_faces(bx, by, bz, i, j, k, q);
-    if (diag(F) > T(0)) {
-      const int c = cell(i, j, k, q);
-      sum += (f[c] - fs) - inv_h2 * flux_sum(F, p, p[c]);
-    }
+  for (int d = 0; d < 4; ++d) {
+    T r0, r1;
+    pair_residual(p, f, bx, by, bz, 2 * I, 2 * J + (d & 1), 2 * K + (d >> 1), q, inv_h2, fs, r0, r1);
+    sum += r0 + r1;
   }
   fc[C] = sum * T(0.125);
   ec[C] = T(0);
 }
 
 // p += mask * trilinear(ec); 1-D weights 3/4 (parent) and 1/4 (nearer neighbour),
-// periodic in x and y, parent reused for a z neighbour outside the grid.
+// periodic in x and y, parent reused for a z neighbour outside the grid.  One thread
+// per coarse cell updates its 8 children (x-pairs on two rows of two planes), applying
+// the 1-D weights in x, then y, then z.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_prolong_add(const T* __restrict__ ec, T* __restrict__ p,
                                                         const uint8_t* __restrict__ mask, int q) {
-  const int m = (1 << q) - 1, qc = q - 1, mc = (1 << qc) - 1;
+  using V2 = typename V2of<T>::type;
+  const int qc = q - 1, mc = (1 << qc) - 1;
   const long long t = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
-  if (t >= (1LL << (3 * q))) return;
-  const int c = static_cast<int>(t);
-  if (!mask[c]) return;
-  const int i = c & m, j = (c >> q) & m, k = c >> (2 * q);
-  const int I = i >> 1, J = j >> 1, K = k >> 1;
-  const int I2 = (I + ((i & 1) ? 1 : -1)) & mc;
-  const int J2 = (J + ((j & 1) ? 1 : -1)) & mc;
-  int K2 = K + ((k & 1) ? 1 : -1);
-  if (K2 < 0 || K2 > mc) K2 = K;
+  if (t >= (1LL << (3 * qc))) return;
+  const int C = static_cast<int>(t);
+  const int I = C & mc, J = (C >> qc) & mc, K = C >> (2 * qc);
+  const int Ix[3] = {(I - 1) & mc, I, (I + 1) & mc};
+  const int Jy[3] = {(J - 1) & mc, J, (J + 1) & mc};
+  const int Kz[3] = {K > 0 ? K - 1 : K, K, K < mc ? K + 1 : K};
   const T w3 = T(0.75), w1 = T(0.25);
-  auto row = [&](int jj, int kk) {   // x interpolation on coarse row (jj, kk)
-    return w3 * ec[cell(I, jj, kk, qc)] + w1 * ec[cell(I2, jj, kk, qc)];
-  };
-  const T lo = w3 * row(J, K) + w1 * row(J2, K);
-  const T hi = w3 * row(J, K2) + w1 * row(J2, K2);
-  p[c] += w3 * lo + w1 * hi;
+  // x interpolation on the 3 x 3 coarse rows around (J, K): even child uses I-1, odd I+1
+  T ax[3][3][2];
+#pragma unroll
+  for (int b = 0; b < 3; ++b)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int row = cell(0, Jy[a], Kz[b], qc);
+      const T e0 = ec[row + Ix[0]], e1 = ec[row + Ix[1]], e2 = ec[row + Ix[2]];
+      ax[b][a][0] = w3 * e1 + w1 * e0;
+      ax[b][a][1] = w3 * e1 + w1 * e2;
+    }
+#pragma unroll
+  for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+    for (int dy = 0; dy < 2; ++dy) {
+      const int kk = 2 * K + dz, jj = 2 * J + dy;
+      const int c = cell(2 * I, jj, kk, q);
+      const uchar2 mk = *reinterpret_cast<const uchar2*>(mask + c);
+      if (!(mk.x | mk.y)) continue;
+      V2 v = *reinterpret_cast<const V2*>(p + c);
+      T out[2];
+#pragma unroll
+      for (int dx = 0; dx < 2; ++dx) {
+        const int ay = dy ? 2 : 0, bz_ = dz ? 2 : 0;   // nearer neighbour row / plane
+        const T lo = w3 * ax[1][1][dx] + w1 * ax[1][ay][dx];
+        const T hi = w3 * ax[bz_][1][dx] + w1 * ax[bz_][ay][dx];
+        out[dx] = w3 * lo + w1 * hi;
+      }
+      if (mk.x) v.x += out[0];
+      if (mk.y) v.y += out[1];
+      *reinterpret_cast<V2*>(p + c) = v;
+    }
 }
 
 // e = A_c^+ (f - active mean of f) on the 4^3 grid, in FP64; one wavefront of 64 lanes.
@@ -290,18 +363,18 @@ __global__ __launch_bounds__(kBlock) void k_residual_norm(const double* __restri
                                                           float* __restrict__ r32, float* __restrict__ e32,
                                                           double* __restrict__ partials) {
   const int m = (1 << q) - 1;
-  const int total = 1 << (3 * q);
+  const int pairs = 1 << (3 * q - 1);
   const double fs = fshift ? *fshift : 0.0;
   double acc = 0.0;
-  for (int c = blockIdx.x * kBlock + threadIdx.x; c < total; c += gridDim.x * kBlock) {
-    const int i = c & m, j = (c >> q) & m, k = c >> (2 * q);
-    const Faces<double> F = load_faces(bx, by, bz, i, j, k, q);
-    double r = 0.0;
-    if (diag(F) > 0.0) r = (f[c] - fs) - inv_h2 * flux_sum(F, p, p[c]);
-    acc += r * r;
+  for (int t = blockIdx.x * kBlock + threadIdx.x; t < pairs; t += gridDim.x * kBlock) {
+    const int i = 2 * (t & (m >> 1)), j = (t >> (q - 1)) & m, k = t >> (2 * q - 1);
+    double r0, r1;
+    pair_residual(p, f, bx, by, bz, i, j, k, q, inv_h2, fs, r0, r1);
+    acc += r0 * r0 + r1 * r1;
     if (r32) {
-      r32[c] = static_cast<float>(r);
-      e32[c] = 0.0f;
+      const int c = cell(i, j, k, q);
+      *reinterpret_cast<float2*>(r32 + c) = float2{static_cast<float>(r0), static_cast<float>(r1)};
+      *reinterpret_cast<float2*>(e32 + c) = float2{0.0f, 0.0f};
     }
   }
   const double s = block_sum(acc);
@@ -406,9 +479,9 @@ __global__ __launch_bounds__(kBlock) void k_coeff_grad(const double* __restrict_
   }
 }
 
-int reduction_blocks(long long total) {
-  long long b = (total + kBlock - 1) / kBlock;
-  return static_cast<int>(b < 2048 ? b : 2048);
+int reduction_blocks(long long work) {
+  long long b = (work + kBlock - 1) / kBlock;
+  return static_cast<int>(b < kNumPartials ? b : kNumPartials);
 }
 
 }  // namespace
@@ -461,7 +534,7 @@ hipError_t launch_residual_restrict(const T* p, const T* f, const T* bx, const T
 
 template <typename T>
 hipError_t launch_prolong_add(const T* ec, T* p, const uint8_t* mask, int q, hipStream_t s) {
-  hipLaunchKernelGGL(k_prolong_add<T>, dim3(grid_for(1LL << (3 * q))), dim3(kBlock), 0, s, ec, p, mask, q);
+  hipLaunchKernelGGL(k_prolong_add<T>, dim3(grid_for(1LL << (3 * (q - 1)))), dim3(kBlock), 0, s, ec, p, mask, q);
   return hipGetLastError();
 }
 
@@ -474,7 +547,7 @@ hipError_t launch_coarse_solve(const T* f, T* e, const double* pinv, const uint8
 hipError_t launch_residual_norm(const double* p, const double* f, const double* bx, const double* by,
                                 const double* bz, int q, double h, const double* fshift, float* r32,
                                 float* e32, double* partials, int* nblocks, hipStream_t s) {
-  const int nb = reduction_blocks(1LL << (3 * q));
+  const int nb = reduction_blocks(1LL << (3 * q - 1));
   hipLaunchKernelGGL(k_residual_norm, dim3(nb), dim3(kBlock), 0, s, p, f, bx, by, bz, q, 1.0 / (h * h), fshift, r32,
                      e32, partials);
   *nblocks = nb;

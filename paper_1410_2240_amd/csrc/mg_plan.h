@@ -15,7 +15,7 @@ namespace mg {
 constexpr int kCoarsest = 4;          // cells per side of the directly solved grid
 constexpr int kMaxN = 1024;           // N^3 < 2^31: 32-bit cell indices throughout
 constexpr int kMaxLevels = 10;        // 1024 -> 4
-constexpr int kNumPartials = 2048;    // blocks of the two-pass reductions
+constexpr int kNumPartials = 16384;   // blocks of the two-pass reductions
 constexpr size_t kAlign = 256;
 
 struct LevelPlan {

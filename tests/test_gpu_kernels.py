@@ -183,3 +183,43 @@ def test_coeff_grad_matches_oracle(problem):
     for got, want in zip(faces, want_faces):
         assert maxrel(host(got), want) <= TOL64
     assert maxrel(host(grho), adjoint.density_gradient(want_faces, H.fine)) <= TOL64
+
+
+# ---------------------------------------------------------------- one-pass fused sweep
+
+@pytest.fixture(scope="module")
+def problem128():
+    from paper_1410_2240_amd import MG
+    N = 128
+    bx, by, bz, mask = raw_problem(N, 4321, body=True, contrast=1000.0)
+    H = omg.setup(bx, by, bz, mask, 1.0 / N)
+    mg = MG(dev(bx), dev(by), dev(bz), dev(mask), mixed=True)
+    return N, H, mg
+
+
+@pytest.mark.parametrize("level", [0, 1])
+@pytest.mark.parametrize("order", [0, 1])
+@pytest.mark.parametrize("sweeps", [1, 2])
+def test_fused_sweep_fp64(problem128, level, order, sweeps):
+    """Grids of 64^3 and up run one red-black sweep per pass (tiles, z-chunks, halos):
+    the result must equal the two half-sweeps of the oracle."""
+    N, H, mg = problem128
+    lev = H.levels[level]
+    g = np.random.default_rng(100 + level)
+    p = np.where(lev.mask, g.standard_normal(lev.bx.shape), 0.0)
+    f = project(g.standard_normal(lev.bx.shape), lev.mask)
+    want = omg.smooth(p, f, lev, sweeps, (omg.RED, omg.BLACK) if order == 0 else (omg.BLACK, omg.RED))
+    got = host(mg.smooth(level, dev(p), dev(f), sweeps, order))
+    assert maxrel(got, want) <= TOL64
+
+
+@pytest.mark.parametrize("order", [0, 1])
+def test_fused_sweep_fp32(problem128, order):
+    N, H, mg = problem128
+    lev32 = omg.fp32_levels(H)[0]
+    g = np.random.default_rng(110)
+    p = f32(np.where(lev32.mask, g.standard_normal(lev32.bx.shape), 0.0))
+    f = f32(project(g.standard_normal(lev32.bx.shape), lev32.mask))
+    want = omg.smooth(p, f, lev32, 2, (omg.RED, omg.BLACK) if order == 0 else (omg.BLACK, omg.RED))
+    got = host(mg.smooth(0, dev(p), dev(f), 2, order))
+    assert maxrel(got, want) <= TOL32
