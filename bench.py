@@ -30,10 +30,15 @@ def parse():
     ap.add_argument("--config", default="c2", help="c1..c5 (default c2: 256^3 wavy interface + body)")
     ap.add_argument("--n", type=int, default=None, help="override the grid size")
     ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--max-cycles", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device copy (HBM counter calibration) and exit")
     return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def main():
@@ -66,29 +71,27 @@ def main():
     mask = torch.from_numpy(inp.mask).to(dev)
     f = torch.from_numpy(inp.f).to(dev)
     t_gen = time.time() - t_gen
+    log(f"inputs {inp.name} {N}^3 generated in {t_gen:.1f} s")
 
-    def projection(mixed):
+    def projection(mixed, krylov=False):
         bx, by, bz = coeffs_from_rho(rho, mask)
-        mg = MG(bx, by, bz, mask, mixed=mixed)
-        p, hist, st = mg.solve(f, tol=args.tol, max_cycles=200)
+        mg = MG(bx, by, bz, mask, mixed=mixed, krylov=krylov)
+        p, hist, st = mg.solve(f, tol=args.tol, max_cycles=args.max_cycles, raise_on_fail=False)
         return mg, p, hist, st
 
-    def timed(mixed, steps, warmup):
+    def timed(mixed, steps, warmup, krylov=False):
         for _ in range(warmup):
-            projection(mixed)
+            projection(mixed, krylov)
         torch.cuda.synchronize()
         start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         start.record()
         cycles = 0
         for _ in range(steps):
-            mg, p, hist, st = projection(mixed)
+            mg, p, hist, st = projection(mixed, krylov)
             cycles += st["cycles"]
         stop.record()
         torch.cuda.synchronize()
-        return start.elapsed_time(stop) / steps, cycles / steps, mg, p, hist
-
-    ms64, cyc64, mg64, p64, hist64 = timed(False, args.steps, args.warmup)
-    msmx, cycmx, mgmx, pmx, histmx = timed(True, max(1, args.steps), 1)
+        return start.elapsed_time(stop) / steps, cycles / steps, mg, p, hist, st["status"]
 
     # pure V-cycle time (10 cycles, no residual checks) in FP64 and FP32
     def vcycle_ms(mg, dtype):
@@ -104,8 +107,9 @@ def main():
         torch.cuda.synchronize()
         return a.elapsed_time(b) / 10
 
+    ms64, cyc64, mg64, p64, hist64, st64 = timed(False, args.steps, args.warmup)
+    log(f"fp64 projection {ms64:.2f} ms, {cyc64:.0f} cycles, status {st64}")
     vc64 = vcycle_ms(mg64, torch.float64)
-    vc32 = vcycle_ms(mgmx, torch.float32)
 
     # dominant kernel: the finest-grid smoother, timed on the stream it runs on
     fz = torch.zeros_like(f)
@@ -123,6 +127,23 @@ def main():
     # algorithmic bytes of one red-black sweep: p, f and three face arrays read, p written
     half_bytes = n * 8 * 6
     achieved = half_bytes / (launch_ms * 1e-3) / 1e9
+    del mg64, p64, fz, ps
+    torch.cuda.empty_cache()
+
+    msmx, cycmx, mgmx, pmx, histmx, stmx = timed(True, max(1, args.steps), 1)
+    log(f"mixed projection {msmx:.2f} ms, {cycmx:.0f} steps, status {stmx}")
+    vc32 = vcycle_ms(mgmx, torch.float32)
+    del mgmx, pmx
+    torch.cuda.empty_cache()
+
+    # flexible CG outer iteration (one V-cycle per step), FP64 and FP32 preconditioner
+    kr = {}
+    for mixed in (False, True):
+        ms, cyc, mgk, pk, hist, st = timed(mixed, max(1, args.steps), 1, krylov=True)
+        kr["mixed" if mixed else "fp64"] = {"ms": ms, "steps": cyc, "final_relres": hist[-1], "status": st}
+        log(f"fcg {'mixed' if mixed else 'fp64'} {ms:.2f} ms, {cyc:.0f} steps, status {st}")
+        del mgk, pk
+        torch.cuda.empty_cache()
 
     out = {
         "metric": "grid-pts/s per V-cycle (FP64 projection: setup + solve to 1e-10)",
@@ -137,6 +158,8 @@ def main():
         "time_to_tol_ms": {"fp64": ms64, "mixed": msmx, "mixed_speedup": ms64 / msmx},
         "cycles_to_tol": {"fp64": cyc64, "mixed_ir_steps": cycmx},
         "final_relres": {"fp64": hist64[-1], "mixed": histmx[-1]},
+        "status": {"fp64": st64, "mixed": stmx},
+        "krylov_fcg": kr,
         "vcycle_ms": {"fp64": vc64, "fp32": vc32},
         "vcycle_pts_per_s": {"fp64": n / (vc64 * 1e-3), "fp32": n / (vc32 * 1e-3)},
         "vcycle_roofline_frac": {"fp64": 35.7 * 8 * n / (vc64 * 1e-3) / (HBM_PEAK_GBS * 1e9),
@@ -147,6 +170,7 @@ def main():
         "input_gen_s": t_gen,
     }
     if not args.no_cpu_baseline:
+        log("timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(inp)
     print(json.dumps(out), flush=True)
 

@@ -60,11 +60,16 @@ enum {
   MG_EBREAKDOWN = -5   /* residual non-finite or grew 1e3-fold; p holds the last iterate */
 };
 
-/* mg_setup flags */
+/* mg_setup flags (MG_MIXED and MG_KRYLOV may be combined) */
 enum {
   MG_FP64 = 0,   /* FP64 V-cycles */
-  MG_MIXED = 1   /* FP32 V-cycles inside FP64 iterative refinement (FP64 residual,
+  MG_MIXED = 1,  /* FP32 V-cycles inside FP64 iterative refinement (FP64 residual,
                     update and coarsest solve); the workspace also holds FP32 copies */
+  MG_KRYLOV = 2  /* outer iteration = flexible conjugate gradients preconditioned by one
+                    V(2,2) cycle per step (FP32 cycle with MG_MIXED); all vector updates
+                    and dot products FP64.  Removes the few error modes a V-cycle misses
+                    at steep, non-grid-aligned density interfaces.  Four more FP64
+                    finest-grid vectors in the workspace. */
 };
 
 /* precision selector of the component entry points */
@@ -74,7 +79,7 @@ enum { MG_PREC_F64 = 0, MG_PREC_F32 = 1 };
 enum { MG_PRE = 0 /* red then black */, MG_POST = 1 /* black then red */ };
 
 typedef struct {
-  int cycles;           /* V-cycles (FP64) or refinement steps (mixed), summed over the batch */
+  int cycles;           /* V-cycles (one per refinement / CG step), summed over the batch */
   int levels;           /* grids in the hierarchy, finest N down to 4 */
   long long active_cells;  /* fluid cells with at least one open face on the finest grid */
   long long dropped_cells; /* fluid cells with no open face: no equation, treated as body */
@@ -118,7 +123,7 @@ int mg_set_stream(mg_ctx* ctx, void* hip_stream);
 /*
  * Solve A p_b = P f_b for b = 0..batch-1 (P removes the fluid mean of f; section 3.1
  * method, V(2,2) cycles until ||P f - A p||_2 / ||P f||_2 <= tol, checked after every
- * cycle or refinement step).  p is in/out: initial guess in, solution out, with zero
+ * cycle, refinement step or CG step).  p is in/out: initial guess in, solution out, with zero
  * fluid mean and 0 in the body.  hist (HOST, may be NULL) receives batch rows of
  * max_cycles+1 relative residuals, hist[b*(max_cycles+1)+0] for the initial guess;
  * n_hist (HOST, may be NULL) receives the entries written per item.  stats may be NULL.

@@ -18,10 +18,10 @@ from .solver import MG
 
 class PoissonSolve(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, f, rho, mask, tol=1e-10, precision="fp64", max_cycles=100):
+    def forward(ctx, f, rho, mask, tol=1e-10, precision="fp64", max_cycles=100, krylov=False):
         if precision not in ("fp64", "mixed"):
             raise ValueError("precision must be 'fp64' or 'mixed'")
-        mg = MG.from_rho(rho.detach().contiguous(), mask.contiguous(), mixed=(precision == "mixed"))
+        mg = MG.from_rho(rho.detach().contiguous(), mask.contiguous(), mixed=(precision == "mixed"), krylov=krylov)
         p, _, stats = mg.solve(f.detach().contiguous(), tol=tol, max_cycles=max_cycles)
         ctx.mg = mg
         ctx.tol = tol
@@ -37,9 +37,9 @@ class PoissonSolve(torch.autograd.Function):
         mu, _, _ = mg.solve(grad_p.contiguous(), tol=ctx.tol, max_cycles=ctx.max_cycles)
         grad_f = mu if ctx.needs_input_grad[0] else None
         grad_rho = mg.coeff_grad(mu, p) if ctx.needs_input_grad[1] else None
-        return grad_f, grad_rho, None, None, None, None
+        return grad_f, grad_rho, None, None, None, None, None
 
 
-def poisson_solve(f, rho, mask, tol=1e-10, precision="fp64", max_cycles=100):
+def poisson_solve(f, rho, mask, tol=1e-10, precision="fp64", max_cycles=100, krylov=False):
     """p with A(rho) p = P f; differentiable in f and rho."""
-    return PoissonSolve.apply(f, rho, mask, tol, precision, max_cycles)
+    return PoissonSolve.apply(f, rho, mask, tol, precision, max_cycles, krylov)

@@ -52,7 +52,7 @@ constexpr double kPinvRtol = 1e-12;
 constexpr double kBreakdownGrowth = 1e3;
 
 // device scalar slots
-enum { S_FMEAN = 0, S_FNORM2 = 1, S_RNORM2 = 2, S_PMEAN = 3, S_COUNT = 8 };
+enum { S_FMEAN = 0, S_FNORM2 = 1, S_RNORM2 = 2, S_PMEAN = 3, S_DW = 4, S_DR = 5, S_ZW = 6, S_COUNT = 8 };
 
 struct Level {
   int n = 0, q = 0;
@@ -80,6 +80,7 @@ struct mg_ctx {
   double* partials = nullptr;
   double* scal = nullptr;
   long long* counters = nullptr;
+  double *kr = nullptr, *kz = nullptr, *kd = nullptr, *kw = nullptr;   // flexible-CG vectors
   double* host = nullptr;   // pinned, S_COUNT doubles
   long long active = 0, dropped = 0;
 
@@ -176,12 +177,22 @@ int read_scalars(mg_ctx* c, double* out, int count) {
   return MG_OK;
 }
 
-// ||r||^2 of the finest residual into scal[S_RNORM2]; optional FP32 copy of r
-int residual_norm(mg_ctx* c, const double* p, const double* f, const double* fshift, float* r32, float* e32) {
+// ||r||^2 of the finest residual into scal[S_RNORM2]; optional FP32 copy of r (with
+// e32 = 0) and FP64 copy (with z64 = 0)
+int residual_norm(mg_ctx* c, const double* p, const double* f, const double* fshift, float* r32, float* e32,
+                  double* r64 = nullptr, double* z64 = nullptr) {
   const Level& a = c->lv[0];
   int nb = 0;
-  MG_HIP(mg::launch_residual_norm(p, f, a.bx, a.by, a.bz, a.q, a.h, fshift, r32, e32, c->partials, &nb, c->stream));
+  MG_HIP(mg::launch_residual_norm(p, f, a.bx, a.by, a.bz, a.q, a.h, fshift, r32, e32, r64, z64, c->partials, &nb,
+                                  c->stream));
   return reduce(c, nb, 1.0, S_RNORM2);
+}
+
+double* part(mg_ctx* c, int set) { return c->partials + static_cast<size_t>(set) * mg::kNumPartials; }
+
+int reduce_set(mg_ctx* c, int set, int nparts, int slot) {
+  MG_HIP(mg::launch_reduce_final(part(c, set), nparts, 1.0, c->scal + slot, c->stream));
+  return MG_OK;
 }
 
 int check_prec(mg_ctx* c, int prec) {
@@ -226,7 +237,49 @@ int solve_one(mg_ctx* c, const double* f, double* p, double tol, int max_cycles,
   if (hist) hist[nh] = r;
   ++nh;
   int status = MG_OK;
-  while (std::isfinite(r) && r > tol && *cycles < max_cycles) {
+  if (c->flags & MG_KRYLOV) {
+    // flexible CG: r, z, d, w in the workspace; z = V(r) in FP64, or V32 on float(r)
+    double *kr = c->kr, *kz = c->kz, *kd = c->kd, *kw = c->kw;
+    const int q = a.q;
+    const float* z32 = mixed ? e32 : nullptr;
+    const double* z64 = mixed ? nullptr : kz;
+    auto precondition = [&]() -> int {
+      if (mixed) return vcycle<float>(c, 0, e32, r32, nullptr);
+      return vcycle<double>(c, 0, kz, kr, nullptr);
+    };
+    if (std::isfinite(r) && r > tol && max_cycles > 0) {
+      // the first residual pass also wrote r (and zeroed the preconditioner output)
+      MG_TRY(residual_norm(c, p, f, fshift, r32, e32, kr, mixed ? nullptr : kz));
+      MG_TRY(precondition());
+      MG_HIP(mg::launch_fcg_dir(z64, z32, kd, nullptr, nullptr, q, c->stream));
+    }
+    while (std::isfinite(r) && r > tol && *cycles < max_cycles) {
+      int nb = 0;
+      MG_HIP(mg::launch_fcg_aw(kd, kr, a.bx, a.by, a.bz, q, a.h, kw, part(c, 0), part(c, 1), &nb, c->stream));
+      MG_TRY(reduce_set(c, 0, nb, S_DW));
+      MG_TRY(reduce_set(c, 1, nb, S_DR));
+      MG_HIP(mg::launch_fcg_update(p, kr, kd, kw, c->scal + S_DR, c->scal + S_DW, q, mixed ? nullptr : kz,
+                                   mixed ? r32 : nullptr, mixed ? e32 : nullptr, part(c, 2), &nb, c->stream));
+      MG_TRY(reduce_set(c, 2, nb, S_RNORM2));
+      ++*cycles;
+      double sn[8];
+      MG_TRY(read_scalars(c, sn, 8));
+      r = std::sqrt(sn[S_RNORM2]) / nf;
+      if (hist) hist[nh] = r;
+      ++nh;
+      if (!std::isfinite(r) || !(sn[S_DW] < 0.0) || r > kBreakdownGrowth * std::fmax(r0, 1.0)) {
+        status = fail(MG_EBREAKDOWN, "flexible CG breakdown after %d steps (residual %g, d.Ad %g)", *cycles, r,
+                      sn[S_DW]);
+        break;
+      }
+      if (r <= tol || *cycles >= max_cycles) break;
+      MG_TRY(precondition());
+      MG_HIP(mg::launch_fcg_zw(z64, z32, kw, q, part(c, 3), &nb, c->stream));
+      MG_TRY(reduce_set(c, 3, nb, S_ZW));
+      MG_HIP(mg::launch_fcg_dir(z64, z32, kd, c->scal + S_ZW, c->scal + S_DW, q, c->stream));
+    }
+  }
+  while (!(c->flags & MG_KRYLOV) && std::isfinite(r) && r > tol && *cycles < max_cycles) {
     if (mixed) {
       // FP32 V-cycle for the correction from the FP32 copy of the FP64 residual, FP64 update
       MG_TRY(vcycle<float>(c, 0, e32, r32, nullptr));
@@ -318,7 +371,7 @@ int mg_setup(mg_ctx** out, void* workspace, size_t ws_bytes, const double* bx, c
   if (mg::validate_dims(dims, &n) != 0) return fail(MG_EINVAL, "dims must be equal powers of two in [8, 1024]");
   if (!bx || !by || !bz || !mask) return fail(MG_EINVAL, "null array pointer");
   if (!(h > 0.0) || !std::isfinite(h)) return fail(MG_EINVAL, "h must be positive and finite");
-  if (flags != MG_FP64 && flags != MG_MIXED) return fail(MG_EINVAL, "unknown flags %d", flags);
+  if (flags < 0 || flags > (MG_MIXED | MG_KRYLOV)) return fail(MG_EINVAL, "unknown flags %d", flags);
   mg::Plan plan;
   if (mg::build_plan(n, flags, &plan) != 0) return fail(MG_EINVAL, "unsupported grid");
   if (!workspace) return fail(MG_EWORKSPACE, "null workspace");
@@ -355,12 +408,16 @@ int mg_setup(mg_ctx** out, void* workspace, size_t ws_bytes, const double* bx, c
   c->partials = at<double>(c->ws, plan.partials);
   c->scal = at<double>(c->ws, plan.scalars);
   c->counters = at<long long>(c->ws, plan.counters);
+  c->kr = at<double>(c->ws, plan.kr);
+  c->kz = at<double>(c->ws, plan.kz);
+  c->kd = at<double>(c->ws, plan.kd);
+  c->kw = at<double>(c->ws, plan.kw);
 
   auto cleanup = [&](int rc) {
     mg_destroy(c);
     return rc;
   };
-  if (hipHostMalloc(reinterpret_cast<void**>(&c->host), sizeof(double) * S_COUNT * 2, hipHostMallocDefault) !=
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->host), sizeof(double) * S_COUNT, hipHostMallocDefault) !=
       hipSuccess) {
     c->host = nullptr;
     return cleanup(fail(MG_EHIP, "hipHostMalloc of the read-back buffer failed"));

@@ -44,10 +44,22 @@ hipError_t launch_coarse_solve(const T* f, T* e, const double* pinv, const uint8
 // ---- FP64 finest-grid passes ------------------------------------------------------
 // partials[blockIdx] = sum over active cells of r^2, r = (f - fshift) - A p; optional
 // r32 = float(r) and e32 = 0 (mixed-precision refinement); returns the block count used.
+// optional outputs: r32 = float(r) with e32 = 0; r64 = r with z64 = 0 (flexible CG)
 hipError_t launch_residual_norm(const double* p, const double* f, const double* bx, const double* by,
                                 const double* bz, int q, double h, const double* fshift,
-                                float* r32, float* e32_zero, double* partials, int* nblocks,
-                                hipStream_t s);
+                                float* r32, float* e32_zero, double* r64, double* z64, double* partials,
+                                int* nblocks, hipStream_t s);
+// flexible CG: w = A d with partial d.w and d.r; the update p += alpha d, r -= alpha w
+// (alpha = dr/dw read on the device) with partial ||r||^2; partial z.w; d = z + beta d
+hipError_t launch_fcg_aw(const double* d, const double* r, const double* bx, const double* by, const double* bz, int q,
+                         double h, double* w, double* part_dw, double* part_dr, int* nblocks, hipStream_t s);
+hipError_t launch_fcg_update(double* p, double* r, const double* d, const double* w, const double* s_dr,
+                             const double* s_dw, int q, double* z_zero, float* r32, float* e32_zero, double* part_rr,
+                             int* nblocks, hipStream_t s);
+hipError_t launch_fcg_zw(const double* z64, const float* z32, const double* w, int q, double* part, int* nblocks,
+                         hipStream_t s);
+hipError_t launch_fcg_dir(const double* z64, const float* z32, double* d, const double* s_zw, const double* s_dw,
+                          int q, hipStream_t s);
 // mode 0: partials = sum_active x ; mode 1: sum_active (x - *shift)^2
 hipError_t launch_masked_sum(const double* x, const uint8_t* mask, int q, int mode, const double* shift,
                              double* partials, int* nblocks, hipStream_t s);

@@ -96,7 +96,7 @@ __device__ __forceinline__ void pair_residual(const T* __restrict__ p, const T* 
   const V2 pyd = ld2(p, cell(i, (j - 1) & m, k, q)), pyu = ld2(p, cell(i, (j + 1) & m, k, q));
   const V2 pzd = k > 0 ? ld2(p, c - nn) : pc;
   const V2 pzu = k < m ? ld2(p, c + nn) : pc;
-  const V2 fv = ld2(f, c);
+  const V2 fv = f ? ld2(f, c) : V2{T(0), T(0)};
   const V2 bxv = ld2(bx, c);
   const T bxr = bx[cell((i + 2) & m, j, k, q)];
   const V2 byv = ld2(by, c), byu = ld2(by, cell(i, (j + 1) & m, k, q));
@@ -361,6 +361,7 @@ __global__ __launch_bounds__(kBlock) void k_residual_norm(const double* __restri
                                                           const double* __restrict__ bz, int q, double inv_h2,
                                                           const double* __restrict__ fshift,
                                                           float* __restrict__ r32, float* __restrict__ e32,
+                                                          double* __restrict__ r64, double* __restrict__ z64,
                                                           double* __restrict__ partials) {
   const int m = (1 << q) - 1;
   const int pairs = 1 << (3 * q - 1);
@@ -371,11 +372,13 @@ __global__ __launch_bounds__(kBlock) void k_residual_norm(const double* __restri
     double r0, r1;
     pair_residual(p, f, bx, by, bz, i, j, k, q, inv_h2, fs, r0, r1);
     acc += r0 * r0 + r1 * r1;
+    const int c = cell(i, j, k, q);
     if (r32) {
-      const int c = cell(i, j, k, q);
       *reinterpret_cast<float2*>(r32 + c) = float2{static_cast<float>(r0), static_cast<float>(r1)};
       *reinterpret_cast<float2*>(e32 + c) = float2{0.0f, 0.0f};
     }
+    if (r64) *reinterpret_cast<double2*>(r64 + c) = double2{r0, r1};
+    if (z64) *reinterpret_cast<double2*>(z64 + c) = double2{0.0, 0.0};
   }
   const double s = block_sum(acc);
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
@@ -479,6 +482,108 @@ __global__ __launch_bounds__(kBlock) void k_coeff_grad(const double* __restrict_
   }
 }
 
+// ---------------------------------------------------------- flexible CG (finest grid, FP64)
+// Vectors are zero on inactive cells.  All loops run over x-pairs with 2-wide loads
+// and end in the fixed-order two-pass block sums.
+
+// w = A d, partial sums of d.w and d.r
+__global__ __launch_bounds__(kBlock) void k_fcg_aw(const double* __restrict__ d, const double* __restrict__ r,
+                                                   const double* __restrict__ bx, const double* __restrict__ by,
+                                                   const double* __restrict__ bz, int q, double inv_h2,
+                                                   double* __restrict__ w, double* __restrict__ part_dw,
+                                                   double* __restrict__ part_dr) {
+  const int m = (1 << q) - 1;
+  const int pairs = 1 << (3 * q - 1);
+  double dw = 0.0, dr = 0.0;
+  for (int t = blockIdx.x * kBlock + threadIdx.x; t < pairs; t += gridDim.x * kBlock) {
+    const int i = 2 * (t & (m >> 1)), j = (t >> (q - 1)) & m, k = t >> (2 * q - 1);
+    double a0, a1;
+    // the residual of f = 0 is -A d
+    pair_residual<double>(d, nullptr, bx, by, bz, i, j, k, q, inv_h2, 0.0, a0, a1);
+    const int c = cell(i, j, k, q);
+    const double2 dv = ld2(d, c), rv = ld2(r, c);
+    const double2 wv = double2{-a0, -a1};
+    *reinterpret_cast<double2*>(w + c) = wv;
+    dw += dv.x * wv.x + dv.y * wv.y;
+    dr += dv.x * rv.x + dv.y * rv.y;
+  }
+  const double s1 = block_sum(dw);
+  const double s2 = block_sum(dr);
+  if (threadIdx.x == 0) {
+    part_dw[blockIdx.x] = s1;
+    part_dr[blockIdx.x] = s2;
+  }
+}
+
+// alpha = dr / dw;  p += alpha d;  r -= alpha w;  partial ||r||^2.  Leaves the next
+// preconditioner input ready: FP64 z = 0, or FP32 r32 = r and e32 = 0.
+__global__ __launch_bounds__(kBlock) void k_fcg_update(double* __restrict__ p, double* __restrict__ r,
+                                                       const double* __restrict__ d, const double* __restrict__ w,
+                                                       const double* __restrict__ s_dr,
+                                                       const double* __restrict__ s_dw, int total,
+                                                       double* __restrict__ z_zero, float* __restrict__ r32,
+                                                       float* __restrict__ e32_zero, double* __restrict__ part_rr) {
+  const double alpha = *s_dr / *s_dw;
+  double rr = 0.0;
+  for (int c = 2 * (blockIdx.x * kBlock + threadIdx.x); c < total; c += 2 * gridDim.x * kBlock) {
+    double2 pv = ld2(p, c), rv = ld2(r, c);
+    const double2 dv = ld2(d, c), wv = ld2(w, c);
+    pv.x += alpha * dv.x;
+    pv.y += alpha * dv.y;
+    rv.x -= alpha * wv.x;
+    rv.y -= alpha * wv.y;
+    *reinterpret_cast<double2*>(p + c) = pv;
+    *reinterpret_cast<double2*>(r + c) = rv;
+    rr += rv.x * rv.x + rv.y * rv.y;
+    if (r32) {
+      *reinterpret_cast<float2*>(r32 + c) = float2{static_cast<float>(rv.x), static_cast<float>(rv.y)};
+      *reinterpret_cast<float2*>(e32_zero + c) = float2{0.0f, 0.0f};
+    } else {
+      *reinterpret_cast<double2*>(z_zero + c) = double2{0.0, 0.0};
+    }
+  }
+  const double s = block_sum(rr);
+  if (threadIdx.x == 0) part_rr[blockIdx.x] = s;
+}
+
+// partial sums of z.w, z in FP64 (z64) or FP32 (z32)
+__global__ __launch_bounds__(kBlock) void k_fcg_zw(const double* __restrict__ z64, const float* __restrict__ z32,
+                                                   const double* __restrict__ w, int total,
+                                                   double* __restrict__ part) {
+  double acc = 0.0;
+  for (int c = 2 * (blockIdx.x * kBlock + threadIdx.x); c < total; c += 2 * gridDim.x * kBlock) {
+    const double2 wv = ld2(w, c);
+    double2 zv;
+    if (z64) {
+      zv = ld2(z64, c);
+    } else {
+      const float2 zf = *reinterpret_cast<const float2*>(z32 + c);
+      zv = double2{static_cast<double>(zf.x), static_cast<double>(zf.y)};
+    }
+    acc += zv.x * wv.x + zv.y * wv.y;
+  }
+  const double s = block_sum(acc);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// d = z + beta d with beta = -zw / dw (beta = 0 when s_zw is null: the first direction)
+__global__ __launch_bounds__(kBlock) void k_fcg_dir(const double* __restrict__ z64, const float* __restrict__ z32,
+                                                    double* __restrict__ d, const double* __restrict__ s_zw,
+                                                    const double* __restrict__ s_dw, int total) {
+  const double beta = s_zw ? -*s_zw / *s_dw : 0.0;
+  const long long c = 2 * (static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x);
+  if (c >= total) return;
+  double2 zv;
+  if (z64) {
+    zv = ld2(z64, static_cast<int>(c));
+  } else {
+    const float2 zf = *reinterpret_cast<const float2*>(z32 + c);
+    zv = double2{static_cast<double>(zf.x), static_cast<double>(zf.y)};
+  }
+  const double2 dv = ld2(d, static_cast<int>(c));
+  *reinterpret_cast<double2*>(d + c) = double2{zv.x + beta * dv.x, zv.y + beta * dv.y};
+}
+
 int reduction_blocks(long long work) {
   long long b = (work + kBlock - 1) / kBlock;
   return static_cast<int>(b < kNumPartials ? b : kNumPartials);
@@ -546,10 +651,11 @@ hipError_t launch_coarse_solve(const T* f, T* e, const double* pinv, const uint8
 
 hipError_t launch_residual_norm(const double* p, const double* f, const double* bx, const double* by,
                                 const double* bz, int q, double h, const double* fshift, float* r32,
-                                float* e32, double* partials, int* nblocks, hipStream_t s) {
+                                float* e32, double* r64, double* z64, double* partials, int* nblocks,
+                                hipStream_t s) {
   const int nb = reduction_blocks(1LL << (3 * q - 1));
   hipLaunchKernelGGL(k_residual_norm, dim3(nb), dim3(kBlock), 0, s, p, f, bx, by, bz, q, 1.0 / (h * h), fshift, r32,
-                     e32, partials);
+                     e32, r64, z64, partials);
   *nblocks = nb;
   return hipGetLastError();
 }
@@ -588,6 +694,40 @@ hipError_t launch_coeff_grad(const double* mu, const double* p, int batch, const
                              double* gbz, double* grho, hipStream_t s) {
   hipLaunchKernelGGL(k_coeff_grad, dim3(grid_for(1LL << (3 * q))), dim3(kBlock), 0, s, mu, p, batch, bx, by, bz, mask,
                      q, 1.0 / (h * h), gbx, gby, gbz, grho);
+  return hipGetLastError();
+}
+
+
+hipError_t launch_fcg_aw(const double* d, const double* r, const double* bx, const double* by, const double* bz, int q,
+                         double h, double* w, double* part_dw, double* part_dr, int* nblocks, hipStream_t s) {
+  const int nb = reduction_blocks(1LL << (3 * q - 1));
+  hipLaunchKernelGGL(k_fcg_aw, dim3(nb), dim3(kBlock), 0, s, d, r, bx, by, bz, q, 1.0 / (h * h), w, part_dw, part_dr);
+  *nblocks = nb;
+  return hipGetLastError();
+}
+
+hipError_t launch_fcg_update(double* p, double* r, const double* d, const double* w, const double* s_dr,
+                             const double* s_dw, int q, double* z_zero, float* r32, float* e32_zero, double* part_rr,
+                             int* nblocks, hipStream_t s) {
+  const int nb = reduction_blocks(1LL << (3 * q - 1));
+  hipLaunchKernelGGL(k_fcg_update, dim3(nb), dim3(kBlock), 0, s, p, r, d, w, s_dr, s_dw, 1 << (3 * q), z_zero, r32,
+                     e32_zero, part_rr);
+  *nblocks = nb;
+  return hipGetLastError();
+}
+
+hipError_t launch_fcg_zw(const double* z64, const float* z32, const double* w, int q, double* part, int* nblocks,
+                         hipStream_t s) {
+  const int nb = reduction_blocks(1LL << (3 * q - 1));
+  hipLaunchKernelGGL(k_fcg_zw, dim3(nb), dim3(kBlock), 0, s, z64, z32, w, 1 << (3 * q), part);
+  *nblocks = nb;
+  return hipGetLastError();
+}
+
+hipError_t launch_fcg_dir(const double* z64, const float* z32, double* d, const double* s_zw, const double* s_dw,
+                          int q, hipStream_t s) {
+  hipLaunchKernelGGL(k_fcg_dir, dim3(grid_for(1LL << (3 * q - 1))), dim3(kBlock), 0, s, z64, z32, d, s_zw, s_dw,
+                     1 << (3 * q));
   return hipGetLastError();
 }
 

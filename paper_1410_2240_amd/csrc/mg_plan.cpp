@@ -31,8 +31,8 @@ int validate_dims(const int dims[3], int* n_out) {
 int build_plan(int n, int flags, Plan* plan) {
   const int d[3] = {n, n, n};
   if (validate_dims(d, nullptr) != 0 || !plan) return -1;
-  if (flags != 0 && flags != 1) return -1;
-  const bool mixed = (flags & 1) != 0;
+  if (flags < 0 || flags > (kFlagMixed | kFlagKrylov)) return -1;
+  const bool mixed = (flags & kFlagMixed) != 0;
   Plan p;
   p.n = n;
   p.flags = flags;
@@ -66,9 +66,16 @@ int build_plan(int n, int flags, Plan* plan) {
       lv.bx32 = lv.by32 = lv.bz32 = lv.f32 = lv.e32 = lv.t32 = kAbsent;
     }
   }
+  if (flags & kFlagKrylov) {
+    const size_t fine = static_cast<size_t>(n) * n * n * 8;
+    p.kr = c.take(fine);
+    p.kz = c.take(fine);
+    p.kd = c.take(fine);
+    p.kw = c.take(fine);
+  }
   const size_t nc = static_cast<size_t>(kCoarsest) * kCoarsest * kCoarsest;
   p.pinv = c.take(nc * nc * 8);
-  p.partials = c.take(kNumPartials * 8);
+  p.partials = c.take(static_cast<size_t>(kPartialSets) * kNumPartials * 8);
   p.scalars = c.take(32 * 8);
   p.counters = c.take(16 * 8);
   p.total = c.off;

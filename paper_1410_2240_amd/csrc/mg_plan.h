@@ -17,6 +17,10 @@ constexpr int kMaxN = 1024;           // N^3 < 2^31: 32-bit cell indices through
 constexpr int kMaxLevels = 10;        // 1024 -> 4
 constexpr int kNumPartials = 16384;   // blocks of the two-pass reductions
 constexpr size_t kAlign = 256;
+constexpr int kPartialSets = 4;       // reductions that may be in flight together
+constexpr int kFlagMixed = 1, kFlagKrylov = 2;
+
+constexpr size_t kAbsent = static_cast<size_t>(-1);
 
 struct LevelPlan {
   int n = 0;         // cells per side
@@ -36,19 +40,20 @@ struct Plan {
   int levels = 0;
   int flags = 0;
   LevelPlan lv[kMaxLevels];
+  // finest-grid FP64 vectors of the flexible-CG outer iteration (Krylov flag only)
+  size_t kr = kAbsent, kz = kAbsent, kd = kAbsent, kw = kAbsent;
   size_t pinv = 0;       // (4^3)^2 doubles: pseudo-inverse of the coarsest operator
-  size_t partials = 0;   // kNumPartials doubles
+  size_t partials = 0;   // kPartialSets x kNumPartials doubles
   size_t scalars = 0;    // 32 doubles of device scalars
   size_t counters = 0;   // 16 int64 counters (setup validation and counts)
   size_t total = 0;      // bytes
 };
 
-constexpr size_t kAbsent = static_cast<size_t>(-1);
-
 // 0 if dims describe a supported cube (equal powers of two, 8..1024), else -1.
 int validate_dims(const int dims[3], int* n_out);
 
-// Fills `plan` for an N^3 grid; returns 0, or -1 for unsupported N or flags.
+// Fills `plan` for an N^3 grid and flags (bit 0 mixed precision, bit 1 flexible CG);
+// returns 0, or -1 for unsupported N or flags.
 int build_plan(int n, int flags, Plan* plan);
 
 }  // namespace mg

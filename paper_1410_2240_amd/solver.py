@@ -12,8 +12,8 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import (MG_EBREAKDOWN, MG_ENOCONV, MG_FP64, MG_MIXED, MG_OK, MG_POST, MG_PRE, MG_PREC_F32,
-                   MG_PREC_F64, MgStats)
+from ._lib import (MG_EBREAKDOWN, MG_ENOCONV, MG_FP64, MG_KRYLOV, MG_MIXED, MG_OK, MG_POST, MG_PRE,
+                   MG_PREC_F32, MG_PREC_F64, MgStats)
 
 
 class MGError(RuntimeError):
@@ -51,8 +51,12 @@ def _grid_n(t: torch.Tensor) -> int:
     return n
 
 
-def workspace_size(n: int, mixed: bool = False) -> int:
-    return int(_lib.load().mg_workspace_size(_lib.dims3(n), MG_MIXED if mixed else MG_FP64))
+def _flags(mixed: bool, krylov: bool) -> int:
+    return (MG_MIXED if mixed else MG_FP64) | (MG_KRYLOV if krylov else 0)
+
+
+def workspace_size(n: int, mixed: bool = False, krylov: bool = False) -> int:
+    return int(_lib.load().mg_workspace_size(_lib.dims3(n), _flags(mixed, krylov)))
 
 
 def coeffs_from_rho(rho: torch.Tensor, mask: torch.Tensor):
@@ -65,30 +69,36 @@ def coeffs_from_rho(rho: torch.Tensor, mask: torch.Tensor):
 
 
 class MG:
-    """A multigrid hierarchy on a caller-owned torch workspace."""
+    """A multigrid hierarchy on a caller-owned torch workspace.
 
-    def __init__(self, bx, by, bz, mask, h: float | None = None, mixed: bool = False):
+    mixed: FP32 V-cycles inside FP64 refinement.  krylov: flexible CG preconditioned
+    by one V-cycle per step (outer iteration), instead of plain V-cycle iteration.
+    """
+
+    def __init__(self, bx, by, bz, mask, h: float | None = None, mixed: bool = False, krylov: bool = False):
         lib = _lib.load()
         n = _grid_n(bx)
         self.n = n
         self.h = 1.0 / n if h is None else float(h)
         self.mixed = bool(mixed)
+        self.krylov = bool(krylov)
         self.device = bx.device
-        size = lib.mg_workspace_size(_lib.dims3(n), MG_MIXED if mixed else MG_FP64)
+        flags = _flags(mixed, krylov)
+        size = lib.mg_workspace_size(_lib.dims3(n), flags)
         if size == 0:
             raise ValueError(f"unsupported grid {n}^3")
         self.workspace = torch.empty(size, dtype=torch.uint8, device=bx.device)
         ctx = ctypes.c_void_p()
         _check(lib.mg_setup(ctypes.byref(ctx), _ptr(self.workspace), size, _ptr(bx, torch.float64),
                             _ptr(by, torch.float64), _ptr(bz, torch.float64), _ptr(mask, torch.uint8),
-                            _lib.dims3(n), self.h, MG_MIXED if mixed else MG_FP64, _stream(bx.device)), "mg_setup")
+                            _lib.dims3(n), self.h, flags, _stream(bx.device)), "mg_setup")
         self._ctx = ctx
         self.levels = lib.mg_level_info(ctx, 0, None, None)
 
     @classmethod
-    def from_rho(cls, rho, mask, h=None, mixed=False):
+    def from_rho(cls, rho, mask, h=None, mixed=False, krylov=False):
         bx, by, bz = coeffs_from_rho(rho, mask)
-        return cls(bx, by, bz, mask, h, mixed)
+        return cls(bx, by, bz, mask, h, mixed, krylov)
 
     def __del__(self):
         ctx = getattr(self, "_ctx", None)

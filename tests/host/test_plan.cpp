@@ -46,14 +46,20 @@ static void check_layout(int n, int flags) {
     } else {
       CHECK(a.f == mg::kAbsent && a.e == mg::kAbsent);
     }
-    if (flags == 1) {
+    if (flags & 1) {
       for (size_t o : {a.bx32, a.by32, a.bz32, a.f32, a.e32, a.t32}) spans.push_back({o, c * 4});
     } else {
       CHECK(a.bx32 == mg::kAbsent && a.f32 == mg::kAbsent);
     }
   }
+  const size_t fine = static_cast<size_t>(n) * n * n * 8;
+  if (flags & 2) {
+    for (size_t o : {p.kr, p.kz, p.kd, p.kw}) spans.push_back({o, fine});
+  } else {
+    CHECK(p.kr == mg::kAbsent && p.kw == mg::kAbsent);
+  }
   spans.push_back({p.pinv, 64 * 64 * 8});
-  spans.push_back({p.partials, mg::kNumPartials * 8});
+  spans.push_back({p.partials, static_cast<size_t>(mg::kPartialSets) * mg::kNumPartials * 8});
   spans.push_back({p.scalars, 32 * 8});
   spans.push_back({p.counters, 16 * 8});
   for (size_t i = 0; i < spans.size(); ++i) {
@@ -74,9 +80,10 @@ int main() {
   for (const auto& d : bad) CHECK(mg::validate_dims(d, nullptr) != 0);
   CHECK(mg::validate_dims(nullptr, nullptr) != 0);
   mg::Plan p;
-  CHECK(mg::build_plan(64, 2, &p) != 0);
+  CHECK(mg::build_plan(64, 4, &p) != 0);
+  CHECK(mg::build_plan(64, -1, &p) != 0);
   for (int m : {8, 16, 64, 256})
-    for (int fl : {0, 1}) check_layout(m, fl);
+    for (int fl : {0, 1, 2, 3}) check_layout(m, fl);
   // 1024^3 FP64: three FP64 face arrays, the mask and the second buffer on the finest grid
   CHECK(mg::build_plan(1024, 0, &p) == 0);
   const double fine = 1024.0 * 1024 * 1024 * (3 * 8 + 1 + 8);

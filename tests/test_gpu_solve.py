@@ -170,3 +170,51 @@ def test_isolated_fluid_cell_dropped():
     f = fields.divergence_rhs(mask)
     p, hist, st = mg.solve(dev(f), tol=1e-12)
     assert st["dropped_cells"] == 1 and host(p)[6, 6, 6] == 0.0
+
+
+# ------------------------------------------------------------------ flexible CG outer iteration
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_fcg_matches_exact_solutions(mixed):
+    from paper_1410_2240_amd import MG
+    for name, N, exact_solve in (("c1", 32, exact.solve_fft_z), ("c2", 32, exact.solve_sparse)):
+        inp, H = workload(name, N)
+        mg = MG.from_rho(dev(inp.rho), dev(inp.mask), mixed=mixed, krylov=True)
+        p, hist, st = mg.solve(dev(inp.f), tol=1e-12, max_cycles=60)
+        assert hist[-1] <= 1e-12 and st["status"] == 0
+        assert relerr(host(p), exact_solve(H.fine, inp.f)) <= 1e-9, (name, mixed)
+
+
+def test_fcg_history_follows_oracle():
+    from paper_1410_2240_amd import MG
+    inp, H = workload("c5", 32)
+    mg = MG.from_rho(dev(inp.rho), dev(inp.mask), krylov=True)
+    p, hist, st = mg.solve(dev(inp.f), tol=1e-12, max_cycles=60)
+    _, ohist = omg.solve_fcg(H, inp.f, tol=1e-12, max_iters=60)
+    # rounding differences grow slowly along a CG recurrence
+    for a, b in list(zip(hist, ohist))[:8]:
+        assert abs(a - b) <= 1e-6 * b + 1e-15
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_fcg_beats_vcycles_on_crest_64(mixed):
+    from paper_1410_2240_amd import MG
+    inp, H = workload("c5", 64)
+    want, _ = omg.solve(H, inp.f, tol=1e-12, max_cycles=200)
+    mg = MG.from_rho(dev(inp.rho), dev(inp.mask), mixed=mixed, krylov=True)
+    p, hist, st = mg.solve(dev(inp.f), tol=1e-12, max_cycles=100)
+    assert relerr(host(p), want) <= 1e-9
+    _, mg_hist, _ = mg_from_inputs(inp, mixed).solve(dev(inp.f), tol=1e-12, max_cycles=200)
+    assert len(hist) < len(mg_hist) / 2
+
+
+def test_crest_256_fcg_residual_by_oracle():
+    """The steep-crest field where V-cycles alone converge slowly: flexible CG to 1e-10,
+    FP64 and mixed, residual recomputed by the oracle."""
+    from paper_1410_2240_amd import MG
+    inp, H = workload("c5", 256)
+    for mixed in (False, True):
+        mg = MG.from_rho(dev(inp.rho), dev(inp.mask), mixed=mixed, krylov=True)
+        p, hist, st = mg.solve(dev(inp.f), tol=1e-10, max_cycles=100)
+        rr = oracle_relres(inp, H, host(p))
+        assert rr <= 1.05e-10, (mixed, rr, len(hist))

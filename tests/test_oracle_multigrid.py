@@ -247,3 +247,50 @@ def test_residual_zero_in_body():
     g = np.random.default_rng(61)
     r = residual(g.standard_normal((8, 8, 8)), project(g.standard_normal((8, 8, 8)), lev.mask), lev)
     assert np.all(r[~lev.mask] == 0)
+
+
+# ------------------------------------------------------------------ flexible CG
+
+def test_fcg_with_identity_preconditioner_is_plain_cg():
+    """With a fixed symmetric preconditioner FCG(1) is preconditioned CG: with B = I its
+    iterates equal scipy's conjugate gradients on the SPD matrix -A (same start, same
+    right-hand side), iteration by iteration."""
+    import scipy.sparse.linalg as spla
+    from oracle.operator import assemble
+    from oracle.multigrid import solve_fcg
+    H = random_hierarchy(8, 90, body=True, contrast=100.0)
+    lev = H.fine
+    f = project(np.random.default_rng(91).standard_normal(lev.bx.shape), lev.mask)
+    M = -assemble(lev)
+    iters = []
+    spla.cg(M, -f.ravel(), x0=np.zeros(f.size), rtol=1e-30, maxiter=6,
+            callback=lambda xk: iters.append(xk.copy()))
+    for k in (1, 3, 6):
+        # hist index k after k iterations; FCG's p is gauge-projected at the end
+        pk, hist = solve_fcg(H, f, tol=1e-300, max_iters=k, precond=lambda r: -r)
+        want = project(iters[k - 1].reshape(f.shape), lev.mask)
+        assert relerr(pk, want) <= 1e-10, k
+
+
+def test_fcg_exact_preconditioner_converges_in_one_step():
+    from oracle.multigrid import solve_fcg
+    H = random_hierarchy(8, 92, body=True, contrast=1000.0)
+    lev = H.fine
+    f = project(np.random.default_rng(93).standard_normal(lev.bx.shape), lev.mask)
+    A = dense_operator(lev)
+    Ap = np.linalg.pinv(A, rcond=1e-12)
+    p, hist = solve_fcg(H, f, tol=1e-12, max_iters=5, precond=lambda r: (Ap @ r.ravel()).reshape(r.shape))
+    assert len(hist) == 2 and hist[-1] <= 1e-12
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_fcg_vcycle_reaches_exact_solution_in_fewer_iterations(mixed):
+    import fields
+    from oracle.multigrid import solve_fcg
+    inp = fields.stokes_crest(32)
+    H = setup(*face_coeffs_from_rho(inp.rho, inp.mask), inp.mask, inp.h)
+    p, hist = solve_fcg(H, inp.f, tol=1e-12, max_iters=60, mixed=mixed)
+    assert hist[-1] <= 1e-12
+    assert relerr(p, exact.solve_sparse(H.fine, inp.f)) < 1e-9
+    _, mg_hist = solve(H, inp.f, tol=1e-12, max_cycles=200)
+    assert len(hist) < len(mg_hist)
