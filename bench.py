@@ -145,6 +145,7 @@ def main():
         del mgk, pk
         torch.cuda.empty_cache()
 
+    traffic = recorded_traffic(inp.name, N)
     out = {
         "metric": "grid-pts/s per V-cycle (FP64 projection: setup + solve to 1e-10)",
         "value": n * cyc64 / (ms64 * 1e-3),
@@ -165,7 +166,7 @@ def main():
         "vcycle_roofline_frac": {"fp64": 35.7 * 8 * n / (vc64 * 1e-3) / (HBM_PEAK_GBS * 1e9),
                                  "fp32": 35.7 * 4 * n / (vc32 * 1e-3) / (HBM_PEAK_GBS * 1e9)},
         "roofline": {"bound": "hbm", "kernel": "rbgs_fused (finest grid, FP64, one red-black sweep)", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "launch_ms": launch_ms, "bytes_per_launch": half_bytes},
         "input_gen_s": t_gen,
     }
@@ -173,6 +174,21 @@ def main():
         log("timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(inp)
     print(json.dumps(out), flush=True)
+
+
+def recorded_traffic(workload, N):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter
+    runs (scaled FETCH_SIZE + WRITE_SIZE), or None when they were taken on another
+    workload or the kernel source has changed since."""
+    import hashlib
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))["k_rbgs_fused<double, 256>"]
+    except (OSError, KeyError, ValueError):
+        return None
+    src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    if hashlib.sha256(src).hexdigest() != rec["source_sha256"] or rec["workload"] != workload or rec["N"] != N:
+        return None
+    return rec["traffic_bytes_per_launch"]
 
 
 def cpu_baseline(inp):
