@@ -65,11 +65,16 @@ enum {
   MG_FP64 = 0,   /* FP64 V-cycles */
   MG_MIXED = 1,  /* FP32 V-cycles inside FP64 iterative refinement (FP64 residual,
                     update and coarsest solve); the workspace also holds FP32 copies */
-  MG_KRYLOV = 2  /* outer iteration = flexible conjugate gradients preconditioned by one
+  MG_KRYLOV = 2, /* outer iteration = flexible conjugate gradients preconditioned by one
                     V(2,2) cycle per step (FP32 cycle with MG_MIXED); all vector updates
                     and dot products FP64.  Removes the few error modes a V-cycle misses
                     at steep, non-grid-aligned density interfaces.  Four more FP64
                     finest-grid vectors in the workspace. */
+  MG_COARSEN_DENSITY = 4 /* mg_setup_from_rho only: the coarsening section 3.1 rejects -
+                    density restricted cell centre to cell centre (mean over active
+                    children), open areas restricted separately (mean of 4 faces), and
+                    beta = area * 2/(rho_L + rho_R) re-formed on every grid.  The finest
+                    operator is unchanged; for comparison with the default. */
 };
 
 /* precision selector of the component entry points */
@@ -116,6 +121,15 @@ int mg_coeffs_from_rho(const double* rho, const uint8_t* mask, const int dims[3]
 int mg_setup(mg_ctx** out, void* workspace, size_t ws_bytes,
              const double* bx, const double* by, const double* bz,
              const uint8_t* mask, const int dims[3], double h, int flags, void* hip_stream);
+
+/*
+ * As mg_setup, but from the cell density: the finest face products
+ * beta_f = o_f 2/(rho_L + rho_R) are formed in the workspace (no caller beta arrays),
+ * then coarsened as one unit (section 3.1), or with MG_COARSEN_DENSITY as density and
+ * area separately.  rho must be positive and finite in fluid cells (MG_EINVAL).
+ */
+int mg_setup_from_rho(mg_ctx** out, void* workspace, size_t ws_bytes, const double* rho,
+                      const uint8_t* mask, const int dims[3], double h, int flags, void* hip_stream);
 
 /* Change the stream used by later calls on this context. */
 int mg_set_stream(mg_ctx* ctx, void* hip_stream);

@@ -300,3 +300,36 @@ def solve_fcg(hier: Hierarchy, f, p0=None, tol: float = 1e-10, max_iters: int = 
         beta = -float(np.sum(z * w)) / dw
         d = z + beta * d
     return project(p, lev.mask), hist
+
+
+def setup_density_coarsening(rho, mask, h, coarsest: int = COARSEST) -> Hierarchy:
+    """The variant section 3.1 rejects: density and cut-surface areas moved to the coarse
+    grids independently, and the face coefficients re-formed on every grid.
+
+      a_0 = o_f (open face), a_{l+1} = mean of the 4 coincident fine face areas;
+      rho_{l+1} = mean of rho over the active children (cell centre to cell centre);
+      beta_l = a_l * 2 / (rho_L + rho_R) on every grid.
+    The finest grid is identical to `setup(face_coeffs_from_rho(rho, mask), ...)`;
+    only the coarse operators differ.  A coarse cell with no active child gets rho = 1
+    (its faces are closed, the value is never used).
+    """
+    from .operator import face_coeffs_from_rho, open_faces
+    m = np.asarray(mask).astype(bool)
+    ox, oy, oz = open_faces(m)
+    areas = Level(ox.astype(np.float64), oy.astype(np.float64), oz.astype(np.float64), m, float(h))
+    areas.mask = m & (diagonal(areas) > 0)
+    rho_l = np.where(areas.mask, np.asarray(rho, np.float64), 1.0)
+    levels = []
+    while True:
+        bx, by, bz = face_coeffs_from_rho(rho_l, np.ones_like(areas.mask))
+        lev = Level(areas.bx * bx, areas.by * by, areas.bz * bz, areas.mask.copy(), areas.h)
+        levels.append(lev)
+        if areas.N <= coarsest:
+            break
+        n = areas.N // 2
+        act = areas.mask.reshape(n, 2, n, 2, n, 2)
+        num = np.where(act, rho_l.reshape(n, 2, n, 2, n, 2), 0.0).sum(axis=(1, 3, 5))
+        cnt = act.sum(axis=(1, 3, 5))
+        areas = coarsen(areas)
+        rho_l = np.where(cnt > 0, num / np.maximum(cnt, 1), 1.0)
+    return Hierarchy(levels, pseudo_inverse(dense_operator(levels[-1])))

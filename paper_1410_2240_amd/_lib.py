@@ -12,7 +12,7 @@ import os
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmgpoisson.so")
 
 MG_OK, MG_EINVAL, MG_EWORKSPACE, MG_EHIP, MG_ENOCONV, MG_EBREAKDOWN = 0, -1, -2, -3, -4, -5
-MG_FP64, MG_MIXED, MG_KRYLOV = 0, 1, 2
+MG_FP64, MG_MIXED, MG_KRYLOV, MG_COARSEN_DENSITY = 0, 1, 2, 4
 MG_PREC_F64, MG_PREC_F32 = 0, 1
 MG_PRE, MG_POST = 0, 1
 
@@ -40,6 +40,7 @@ SIGNATURES = {
     "mg_workspace_size": (ctypes.c_size_t, [_DIMS, _I]),
     "mg_coeffs_from_rho": (_I, [_P, _P, _DIMS, _P, _P, _P, _P]),
     "mg_setup": (_I, [ctypes.POINTER(_P), _P, ctypes.c_size_t, _P, _P, _P, _P, _DIMS, _D, _I, _P]),
+    "mg_setup_from_rho": (_I, [ctypes.POINTER(_P), _P, ctypes.c_size_t, _P, _P, _DIMS, _D, _I, _P]),
     "mg_set_stream": (_I, [_P, _P]),
     "mg_solve": (_I, [_P, _P, _P, _I, _D, _I, ctypes.POINTER(_D), ctypes.POINTER(_I), ctypes.POINTER(MgStats)]),
     "mg_apply": (_I, [_P, _P, _P, _I]),

@@ -341,37 +341,23 @@ int check_level(mg_ctx* c, int level, int need_coarser) {
 
 }  // namespace
 
-extern "C" {
+extern "C" void mg_destroy(mg_ctx* ctx);
 
-const char* mg_last_error(void) { return g_error.c_str(); }
+namespace {
 
-size_t mg_workspace_size(const int dims[3], int flags) {
-  int n = 0;
-  mg::Plan plan;
-  if (mg::validate_dims(dims, &n) != 0 || mg::build_plan(n, flags, &plan) != 0) return 0;
-  return plan.total;
-}
-
-int mg_coeffs_from_rho(const double* rho, const uint8_t* mask, const int dims[3], double* bx, double* by, double* bz,
-                       void* hip_stream) {
-  int n = 0;
-  if (mg::validate_dims(dims, &n) != 0) return fail(MG_EINVAL, "dims must be equal powers of two in [8, 1024]");
-  if (!rho || !mask || !bx || !by || !bz) return fail(MG_EINVAL, "null array pointer");
-  int q = 0;
-  while ((1 << q) < n) ++q;
-  MG_HIP(mg::launch_coeffs_from_rho(rho, mask, q, bx, by, bz, static_cast<hipStream_t>(hip_stream)));
-  return MG_OK;
-}
-
-int mg_setup(mg_ctx** out, void* workspace, size_t ws_bytes, const double* bx, const double* by, const double* bz,
-             const uint8_t* mask, const int dims[3], double h, int flags, void* hip_stream) {
+// Shared by mg_setup (finest face coefficients given) and mg_setup_from_rho (cell
+// density given; face products formed here, or density and areas coarsened apart).
+int setup_impl(mg_ctx** out, void* workspace, size_t ws_bytes, const double* bx, const double* by, const double* bz,
+               const double* rho, const uint8_t* mask, const int dims[3], double h, int flags, void* hip_stream) {
   if (!out) return fail(MG_EINVAL, "null output pointer");
   *out = nullptr;
   int n = 0;
   if (mg::validate_dims(dims, &n) != 0) return fail(MG_EINVAL, "dims must be equal powers of two in [8, 1024]");
-  if (!bx || !by || !bz || !mask) return fail(MG_EINVAL, "null array pointer");
+  if (!mask || (!rho && (!bx || !by || !bz))) return fail(MG_EINVAL, "null array pointer");
   if (!(h > 0.0) || !std::isfinite(h)) return fail(MG_EINVAL, "h must be positive and finite");
-  if (flags < 0 || flags > (MG_MIXED | MG_KRYLOV)) return fail(MG_EINVAL, "unknown flags %d", flags);
+  if (flags < 0 || flags > (MG_MIXED | MG_KRYLOV | MG_COARSEN_DENSITY)) return fail(MG_EINVAL, "unknown flags %d", flags);
+  const bool density = (flags & MG_COARSEN_DENSITY) != 0;
+  if (density && !rho) return fail(MG_EINVAL, "density coarsening needs the cell density (mg_setup_from_rho)");
   mg::Plan plan;
   if (mg::build_plan(n, flags, &plan) != 0) return fail(MG_EINVAL, "unsupported grid");
   if (!workspace) return fail(MG_EWORKSPACE, "null workspace");
@@ -429,11 +415,31 @@ int mg_setup(mg_ctx** out, void* workspace, size_t ws_bytes, const double* bx, c
   };
   hip(hipMemsetAsync(c->counters, 0, 16 * sizeof(long long), s), "hipMemsetAsync(counters)");
   Level& f0 = c->lv[0];
-  hip(mg::launch_setup_fine(bx, by, bz, mask, f0.q, f0.bx, f0.by, f0.bz, f0.mask, c->counters, s), "setup_fine");
+  if (rho) {
+    // face products (or, for density coarsening, open-face areas) straight into the
+    // workspace, then validation and activity without rewriting them
+    hip(mg::launch_coeffs_from_rho(density ? nullptr : rho, mask, f0.q, f0.bx, f0.by, f0.bz, s), "coeffs_from_rho");
+    hip(mg::launch_setup_fine(f0.bx, f0.by, f0.bz, mask, f0.q, nullptr, nullptr, nullptr, f0.mask, c->counters, s),
+        "setup_fine");
+  } else {
+    hip(mg::launch_setup_fine(bx, by, bz, mask, f0.q, f0.bx, f0.by, f0.bz, f0.mask, c->counters, s), "setup_fine");
+  }
   for (int l = 1; l < c->L; ++l) {
     const Level& a = c->lv[l - 1];
     Level& b = c->lv[l];
     hip(mg::launch_coarsen(a.bx, a.by, a.bz, a.mask, b.q, b.bx, b.by, b.bz, b.mask, s), "coarsen");
+  }
+  if (density) {
+    // the coarsening section 3.1 rejects: density restricted cell centre to cell centre
+    // (held in each level's second buffer), areas as above, faces re-formed per level
+    for (int l = 1; l < c->L; ++l) {
+      const double* fine_rho = l == 1 ? rho : c->lv[l - 1].t;
+      hip(mg::launch_restrict_rho(fine_rho, c->lv[l - 1].mask, c->lv[l].q, c->lv[l].t, s), "restrict_rho");
+    }
+    for (int l = 0; l < c->L; ++l) {
+      Level& a = c->lv[l];
+      hip(mg::launch_area_to_beta(l == 0 ? rho : a.t, a.q, a.bx, a.by, a.bz, s), "area_to_beta");
+    }
   }
   if (flags & MG_MIXED) {
     for (int l = 0; l < c->L; ++l) {
@@ -456,7 +462,9 @@ int mg_setup(mg_ctx** out, void* workspace, size_t ws_bytes, const double* bx, c
   hip(hipMemcpyAsync(cnt, c->counters, sizeof cnt, hipMemcpyDeviceToHost, s), "copy counters");
   hip(hipStreamSynchronize(s), "hipStreamSynchronize(setup)");
   if (rc != MG_OK) return cleanup(rc);
-  if (cnt[0] > 0) return cleanup(fail(MG_EINVAL, "%lld face coefficients are negative or not finite", cnt[0]));
+  if (cnt[0] > 0)
+    return cleanup(fail(MG_EINVAL, "%lld face coefficients are negative or not finite%s", cnt[0],
+                        rho ? " (density must be positive and finite in fluid cells)" : ""));
   if (cnt[1] == 0) return cleanup(fail(MG_EINVAL, "no fluid cell has an open face"));
   c->active = cnt[1];
   c->dropped = cnt[2];
@@ -467,6 +475,43 @@ int mg_setup(mg_ctx** out, void* workspace, size_t ws_bytes, const double* bx, c
   if (rc != MG_OK) return cleanup(rc);
   *out = c;
   return MG_OK;
+}
+
+
+}  // namespace
+
+extern "C" {
+
+const char* mg_last_error(void) { return g_error.c_str(); }
+
+size_t mg_workspace_size(const int dims[3], int flags) {
+  int n = 0;
+  mg::Plan plan;
+  if (mg::validate_dims(dims, &n) != 0 || mg::build_plan(n, flags, &plan) != 0) return 0;
+  return plan.total;
+}
+
+int mg_coeffs_from_rho(const double* rho, const uint8_t* mask, const int dims[3], double* bx, double* by, double* bz,
+                       void* hip_stream) {
+  int n = 0;
+  if (mg::validate_dims(dims, &n) != 0) return fail(MG_EINVAL, "dims must be equal powers of two in [8, 1024]");
+  if (!rho || !mask || !bx || !by || !bz) return fail(MG_EINVAL, "null array pointer");
+  int q = 0;
+  while ((1 << q) < n) ++q;
+  MG_HIP(mg::launch_coeffs_from_rho(rho, mask, q, bx, by, bz, static_cast<hipStream_t>(hip_stream)));
+  return MG_OK;
+}
+
+
+int mg_setup(mg_ctx** out, void* workspace, size_t ws_bytes, const double* bx, const double* by, const double* bz,
+             const uint8_t* mask, const int dims[3], double h, int flags, void* hip_stream) {
+  return setup_impl(out, workspace, ws_bytes, bx, by, bz, nullptr, mask, dims, h, flags, hip_stream);
+}
+
+int mg_setup_from_rho(mg_ctx** out, void* workspace, size_t ws_bytes, const double* rho, const uint8_t* mask,
+                      const int dims[3], double h, int flags, void* hip_stream) {
+  if (!rho) return fail(MG_EINVAL, "null density pointer");
+  return setup_impl(out, workspace, ws_bytes, nullptr, nullptr, nullptr, rho, mask, dims, h, flags, hip_stream);
 }
 
 int mg_set_stream(mg_ctx* ctx, void* hip_stream) {

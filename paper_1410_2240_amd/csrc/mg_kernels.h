@@ -11,9 +11,15 @@
 namespace mg {
 
 // ---- setup --------------------------------------------------------------------
+// beta_f = o_f 2/(rho_L + rho_R); with rho == nullptr the open-face areas o_f (0 or 1)
 hipError_t launch_coeffs_from_rho(const double* rho, const uint8_t* mask, int q,
                                   double* bx, double* by, double* bz, hipStream_t s);
-// counters[0] += non-finite or negative beta values, [1] += active cells, [2] += dropped
+// coarse rho = mean of rho over the active children (1 if none)
+hipError_t launch_restrict_rho(const double* rho, const uint8_t* mask, int qc, double* crho, hipStream_t s);
+// beta = area * 2/(rho_L + rho_R) in place on the open faces
+hipError_t launch_area_to_beta(const double* rho, int q, double* bx, double* by, double* bz, hipStream_t s);
+// counters[0] += non-finite or negative beta values, [1] += active cells, [2] += dropped;
+// bx == nullptr: validate and mark only (the coefficients are already closed in place)
 hipError_t launch_setup_fine(const double* ubx, const double* uby, const double* ubz,
                              const uint8_t* umask, int q, double* bx, double* by, double* bz,
                              uint8_t* mask, long long* counters, hipStream_t s);

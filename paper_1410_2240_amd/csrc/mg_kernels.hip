@@ -125,10 +125,52 @@ __global__ __launch_bounds__(kBlock) void k_coeffs_from_rho(const double* __rest
   const int i = c & m, j = (c >> q) & m, k = c >> (2 * q);
   const bool mc = mask[c] != 0;
   const int cx = cell((i - 1) & m, j, k, q), cy = cell(i, (j - 1) & m, k, q);
-  bx[c] = (mc && mask[cx]) ? 2.0 / (rho[c] + rho[cx]) : 0.0;
-  by[c] = (mc && mask[cy]) ? 2.0 / (rho[c] + rho[cy]) : 0.0;
   const int cz = c - (1 << (2 * q));
-  bz[c] = (k > 0 && mc && mask[cz]) ? 2.0 / (rho[c] + rho[cz]) : 0.0;
+  const bool ox = mc && mask[cx], oy = mc && mask[cy], oz = k > 0 && mc && mask[cz];
+  if (!rho) {   // open-face areas only
+    bx[c] = ox ? 1.0 : 0.0;
+    by[c] = oy ? 1.0 : 0.0;
+    bz[c] = oz ? 1.0 : 0.0;
+    return;
+  }
+  bx[c] = ox ? 2.0 / (rho[c] + rho[cx]) : 0.0;
+  by[c] = oy ? 2.0 / (rho[c] + rho[cy]) : 0.0;
+  bz[c] = oz ? 2.0 / (rho[c] + rho[cz]) : 0.0;
+}
+
+// Density moved cell centre to cell centre: mean over the active children, 1 when
+// there is none (such a coarse cell has only closed faces).
+__global__ __launch_bounds__(kBlock) void k_restrict_rho(const double* __restrict__ rho, const uint8_t* __restrict__ mask,
+                                                         int qc, double* __restrict__ crho) {
+  const int mc = (1 << qc) - 1, q = qc + 1;
+  const long long t = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
+  if (t >= (1LL << (3 * qc))) return;
+  const int C = static_cast<int>(t);
+  const int I = C & mc, J = (C >> qc) & mc, K = C >> (2 * qc);
+  double sum = 0.0;
+  int cnt = 0;
+  for (int d = 0; d < 8; ++d) {
+    const int c = cell(2 * I + (d & 1), 2 * J + ((d >> 1) & 1), 2 * K + (d >> 2), q);
+    if (mask[c]) {
+      sum += rho[c];
+      ++cnt;
+    }
+  }
+  crho[C] = cnt ? sum / cnt : 1.0;
+}
+
+// beta = area * 2 / (rho_L + rho_R) in place (closed faces stay 0)
+__global__ __launch_bounds__(kBlock) void k_area_to_beta(const double* __restrict__ rho, int q, double* __restrict__ bx,
+                                                         double* __restrict__ by, double* __restrict__ bz) {
+  const int m = (1 << q) - 1;
+  const long long t = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
+  if (t >= (1LL << (3 * q))) return;
+  const int c = static_cast<int>(t);
+  const int i = c & m, j = (c >> q) & m, k = c >> (2 * q);
+  const double ax = bx[c], ay = by[c], az = bz[c];
+  if (ax != 0.0) bx[c] = ax * (2.0 / (rho[c] + rho[cell((i - 1) & m, j, k, q)]));
+  if (ay != 0.0) by[c] = ay * (2.0 / (rho[c] + rho[cell(i, (j - 1) & m, k, q)]));
+  if (az != 0.0) bz[c] = az * (2.0 / (rho[c] + rho[c - (1 << (2 * q))]));
 }
 
 __global__ __launch_bounds__(kBlock) void k_setup_fine(const double* __restrict__ ubx, const double* __restrict__ uby,
@@ -157,9 +199,11 @@ __global__ __launch_bounds__(kBlock) void k_setup_fine(const double* __restrict_
     const double xp = (mc && umask[cxp]) ? ubx[cxp] : 0.0;
     const double yp = (mc && umask[cyp]) ? uby[cyp] : 0.0;
     const double zp = (k < m && mc && umask[c + nn]) ? ubz[c + nn] : 0.0;
-    bx[c] = xm;
-    by[c] = ym;
-    bz[c] = zm;
+    if (bx) {
+      bx[c] = xm;
+      by[c] = ym;
+      bz[c] = zm;
+    }
     const bool act = mc && (xm + xp + ym + yp + zm + zp) > 0.0;
     mask[c] = act ? 1 : 0;
     active = act;
@@ -604,6 +648,16 @@ hipError_t launch_setup_fine(const double* ubx, const double* uby, const double*
                              hipStream_t s) {
   hipLaunchKernelGGL(k_setup_fine, dim3(grid_for(1LL << (3 * q))), dim3(kBlock), 0, s, ubx, uby, ubz, umask, q, bx,
                      by, bz, mask, counters);
+  return hipGetLastError();
+}
+
+hipError_t launch_restrict_rho(const double* rho, const uint8_t* mask, int qc, double* crho, hipStream_t s) {
+  hipLaunchKernelGGL(k_restrict_rho, dim3(grid_for(1LL << (3 * qc))), dim3(kBlock), 0, s, rho, mask, qc, crho);
+  return hipGetLastError();
+}
+
+hipError_t launch_area_to_beta(const double* rho, int q, double* bx, double* by, double* bz, hipStream_t s) {
+  hipLaunchKernelGGL(k_area_to_beta, dim3(grid_for(1LL << (3 * q))), dim3(kBlock), 0, s, rho, q, bx, by, bz);
   return hipGetLastError();
 }
 

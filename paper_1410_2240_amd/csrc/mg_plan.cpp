@@ -31,7 +31,7 @@ int validate_dims(const int dims[3], int* n_out) {
 int build_plan(int n, int flags, Plan* plan) {
   const int d[3] = {n, n, n};
   if (validate_dims(d, nullptr) != 0 || !plan) return -1;
-  if (flags < 0 || flags > (kFlagMixed | kFlagKrylov)) return -1;
+  if (flags < 0 || flags > (kFlagMixed | kFlagKrylov | kFlagDensity)) return -1;
   const bool mixed = (flags & kFlagMixed) != 0;
   Plan p;
   p.n = n;

@@ -18,7 +18,7 @@ constexpr int kMaxLevels = 10;        // 1024 -> 4
 constexpr int kNumPartials = 16384;   // blocks of the two-pass reductions
 constexpr size_t kAlign = 256;
 constexpr int kPartialSets = 4;       // reductions that may be in flight together
-constexpr int kFlagMixed = 1, kFlagKrylov = 2;
+constexpr int kFlagMixed = 1, kFlagKrylov = 2, kFlagDensity = 4;
 
 constexpr size_t kAbsent = static_cast<size_t>(-1);
 
@@ -52,7 +52,8 @@ struct Plan {
 // 0 if dims describe a supported cube (equal powers of two, 8..1024), else -1.
 int validate_dims(const int dims[3], int* n_out);
 
-// Fills `plan` for an N^3 grid and flags (bit 0 mixed precision, bit 1 flexible CG);
+// Fills `plan` for an N^3 grid and flags (bit 0 mixed precision, bit 1 flexible CG,
+// bit 2 density coarsening, which needs no extra storage);
 // returns 0, or -1 for unsupported N or flags.
 int build_plan(int n, int flags, Plan* plan);
 

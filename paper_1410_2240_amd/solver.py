@@ -12,8 +12,8 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import (MG_EBREAKDOWN, MG_ENOCONV, MG_FP64, MG_KRYLOV, MG_MIXED, MG_OK, MG_POST, MG_PRE,
-                   MG_PREC_F32, MG_PREC_F64, MgStats)
+from ._lib import (MG_COARSEN_DENSITY, MG_EBREAKDOWN, MG_ENOCONV, MG_FP64, MG_KRYLOV, MG_MIXED, MG_OK,
+                   MG_POST, MG_PRE, MG_PREC_F32, MG_PREC_F64, MgStats)
 
 
 class MGError(RuntimeError):
@@ -75,30 +75,41 @@ class MG:
     by one V-cycle per step (outer iteration), instead of plain V-cycle iteration.
     """
 
-    def __init__(self, bx, by, bz, mask, h: float | None = None, mixed: bool = False, krylov: bool = False):
+    def __init__(self, bx, by, bz, mask, h: float | None = None, mixed: bool = False, krylov: bool = False,
+                 _rho=None, _density_coarsening: bool = False):
         lib = _lib.load()
-        n = _grid_n(bx)
+        ref = bx if _rho is None else _rho
+        n = _grid_n(ref)
         self.n = n
         self.h = 1.0 / n if h is None else float(h)
         self.mixed = bool(mixed)
         self.krylov = bool(krylov)
-        self.device = bx.device
-        flags = _flags(mixed, krylov)
+        self.device = ref.device
+        flags = _flags(mixed, krylov) | (MG_COARSEN_DENSITY if _density_coarsening else 0)
         size = lib.mg_workspace_size(_lib.dims3(n), flags)
         if size == 0:
             raise ValueError(f"unsupported grid {n}^3")
-        self.workspace = torch.empty(size, dtype=torch.uint8, device=bx.device)
+        self.workspace = torch.empty(size, dtype=torch.uint8, device=ref.device)
         ctx = ctypes.c_void_p()
-        _check(lib.mg_setup(ctypes.byref(ctx), _ptr(self.workspace), size, _ptr(bx, torch.float64),
-                            _ptr(by, torch.float64), _ptr(bz, torch.float64), _ptr(mask, torch.uint8),
-                            _lib.dims3(n), self.h, flags, _stream(bx.device)), "mg_setup")
+        if _rho is None:
+            rc = lib.mg_setup(ctypes.byref(ctx), _ptr(self.workspace), size, _ptr(bx, torch.float64),
+                              _ptr(by, torch.float64), _ptr(bz, torch.float64), _ptr(mask, torch.uint8),
+                              _lib.dims3(n), self.h, flags, _stream(ref.device))
+        else:
+            rc = lib.mg_setup_from_rho(ctypes.byref(ctx), _ptr(self.workspace), size, _ptr(_rho, torch.float64),
+                                       _ptr(mask, torch.uint8), _lib.dims3(n), self.h, flags, _stream(ref.device))
+        _check(rc, "mg_setup")
         self._ctx = ctx
         self.levels = lib.mg_level_info(ctx, 0, None, None)
 
     @classmethod
-    def from_rho(cls, rho, mask, h=None, mixed=False, krylov=False):
-        bx, by, bz = coeffs_from_rho(rho, mask)
-        return cls(bx, by, bz, mask, h, mixed, krylov)
+    def from_rho(cls, rho, mask, h=None, mixed=False, krylov=False, coarsening="face"):
+        """Hierarchy from the cell density.  coarsening = "face" moves the face products
+        to the coarse grids (section 3.1); "density" restricts density and areas apart,
+        the variant the paper rejects (for comparison)."""
+        if coarsening not in ("face", "density"):
+            raise ValueError("coarsening must be 'face' or 'density'")
+        return cls(None, None, None, mask, h, mixed, krylov, _rho=rho, _density_coarsening=coarsening == "density")
 
     def __del__(self):
         ctx = getattr(self, "_ctx", None)

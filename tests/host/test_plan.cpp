@@ -80,10 +80,15 @@ int main() {
   for (const auto& d : bad) CHECK(mg::validate_dims(d, nullptr) != 0);
   CHECK(mg::validate_dims(nullptr, nullptr) != 0);
   mg::Plan p;
-  CHECK(mg::build_plan(64, 4, &p) != 0);
+  CHECK(mg::build_plan(64, 8, &p) != 0);
   CHECK(mg::build_plan(64, -1, &p) != 0);
   for (int m : {8, 16, 64, 256})
     for (int fl : {0, 1, 2, 3}) check_layout(m, fl);
+  // density coarsening needs no storage of its own
+  {
+    mg::Plan pa, pb;
+    CHECK(mg::build_plan(64, 3, &pa) == 0 && mg::build_plan(64, 7, &pb) == 0 && pa.total == pb.total);
+  }
   // 1024^3 FP64: three FP64 face arrays, the mask and the second buffer on the finest grid
   CHECK(mg::build_plan(1024, 0, &p) == 0);
   const double fine = 1024.0 * 1024 * 1024 * (3 * 8 + 1 + 8);

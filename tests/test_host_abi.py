@@ -49,4 +49,5 @@ def test_workspace_size_is_host_arithmetic():
     assert s32 - s64 > n * 6 * 4
     assert lib.mg_workspace_size(_lib.dims3(48), 0) == 0
     assert lib.mg_workspace_size((ctypes.c_int * 3)(64, 64, 32), 0) == 0
-    assert lib.mg_workspace_size(_lib.dims3(64), 7) == 0
+    assert lib.mg_workspace_size(_lib.dims3(64), 8) == 0
+    assert lib.mg_workspace_size(_lib.dims3(64), 4) == lib.mg_workspace_size(_lib.dims3(64), 0)

@@ -294,3 +294,38 @@ def test_fcg_vcycle_reaches_exact_solution_in_fewer_iterations(mixed):
     assert relerr(p, exact.solve_sparse(H.fine, inp.f)) < 1e-9
     _, mg_hist = solve(H, inp.f, tol=1e-12, max_cycles=200)
     assert len(hist) < len(mg_hist)
+
+
+# ------------------------------------------------------------------ coarsening ablation
+
+def test_density_coarsening_same_fine_grid_and_constant_case():
+    import fields
+    from oracle.multigrid import setup_density_coarsening
+    inp = fields.wavy_body(16)
+    Hf = setup(*face_coeffs_from_rho(inp.rho, inp.mask), inp.mask, inp.h)
+    Hd = setup_density_coarsening(inp.rho, inp.mask, inp.h)
+    for a, b in ((Hf.fine.bx, Hd.fine.bx), (Hf.fine.by, Hd.fine.by), (Hf.fine.bz, Hd.fine.bz)):
+        assert np.array_equal(a, b)
+    assert all(np.array_equal(a.mask, b.mask) for a, b in zip(Hf.levels, Hd.levels))
+    # constant density: both ways of coarsening give the same operators
+    rho = np.full((16, 16, 16), 0.25)
+    Hf = setup(*face_coeffs_from_rho(rho, inp.mask), inp.mask, inp.h)
+    Hd = setup_density_coarsening(rho, inp.mask, inp.h)
+    for a, b in zip(Hf.levels, Hd.levels):
+        assert np.allclose(a.bx, b.bx, rtol=1e-15) and np.allclose(a.bz, b.bz, rtol=1e-15)
+
+
+def test_density_coarsening_smooths_a_sharp_interface():
+    """Two planes of water (rho 1) under two of air (1e-3): after one coarsening the
+    face-product grid keeps 1/rho on the air plane's x faces, while averaging density
+    first gives 2/(1 + 1e-3) on the interface plane - the interface is smeared."""
+    N = 8
+    rho = np.ones((N, N, N))
+    rho[1:] = 1e-3          # water at k = 0; air above (the coarse cell K=0 straddles)
+    m = np.ones((N, N, N), np.uint8)
+    from oracle.multigrid import setup_density_coarsening
+    Hf = setup(*face_coeffs_from_rho(rho, m), m, 1.0 / N)
+    Hd = setup_density_coarsening(rho, m, 1.0 / N)
+    # coarse K = 0 holds fine planes k = 0 (water) and k = 1 (air)
+    assert Hf.levels[1].bx[0, 0, 0] == pytest.approx(0.5 * (1.0 + 1e3))
+    assert Hd.levels[1].bx[0, 0, 0] == pytest.approx(1.0 / (0.5 * (1.0 + 1e-3)))
