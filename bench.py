@@ -61,7 +61,7 @@ def main():
         return
 
     import fields
-    from paper_1410_2240_amd import MG, coeffs_from_rho
+    from paper_1410_2240_amd import MG
 
     t_gen = time.time()
     inp = fields.make(args.config, args.n)
@@ -74,8 +74,8 @@ def main():
     log(f"inputs {inp.name} {N}^3 generated in {t_gen:.1f} s")
 
     def projection(mixed, krylov=False):
-        bx, by, bz = coeffs_from_rho(rho, mask)
-        mg = MG(bx, by, bz, mask, mixed=mixed, krylov=krylov)
+        # face products from rho formed in the workspace, hierarchy, solve
+        mg = MG.from_rho(rho, mask, mixed=mixed, krylov=krylov)
         p, hist, st = mg.solve(f, tol=args.tol, max_cycles=args.max_cycles, raise_on_fail=False)
         return mg, p, hist, st
 

@@ -20,6 +20,8 @@
 
 namespace mg {
 void symmetric_pinv(int n, std::vector<double>& a, double rtol, std::vector<double>& pinv);
+bool graph_pinv(int n, const std::vector<double>& a, const std::vector<int>& component, double rtol,
+                std::vector<double>& pinv);
 }
 
 namespace {
@@ -333,6 +335,37 @@ void coarse_dense(const std::vector<double>& bx, const std::vector<double>& by, 
       }
 }
 
+// connected components of the active cells of the coarsest grid over faces with
+// beta > 0; inactive cells get -1
+std::vector<int> coarse_components(const std::vector<double>& bx, const std::vector<double>& by,
+                                   const std::vector<double>& bz, const std::vector<uint8_t>& mask, int n) {
+  const int nc = n * n * n;
+  std::vector<int> comp(nc, -1);
+  auto id = [n](int i, int j, int k) { return (k * n + j) * n + i; };
+  int next = 0;
+  std::vector<int> stack;
+  for (int s0 = 0; s0 < nc; ++s0) {
+    if (!mask[s0] || comp[s0] >= 0) continue;
+    comp[s0] = next;
+    stack.assign(1, s0);
+    while (!stack.empty()) {
+      const int c = stack.back();
+      stack.pop_back();
+      const int i = c % n, j = (c / n) % n, k = c / (n * n);
+      const int nb[6] = {id((i + n - 1) % n, j, k), id((i + 1) % n, j, k), id(i, (j + n - 1) % n, k),
+                         id(i, (j + 1) % n, k), k > 0 ? id(i, j, k - 1) : -1, k < n - 1 ? id(i, j, k + 1) : -1};
+      const double b[6] = {bx[c], bx[nb[1]], by[c], by[nb[3]], bz[c], k < n - 1 ? bz[nb[5]] : 0.0};
+      for (int f = 0; f < 6; ++f)
+        if (nb[f] >= 0 && b[f] > 0.0 && mask[nb[f]] && comp[nb[f]] < 0) {
+          comp[nb[f]] = next;
+          stack.push_back(nb[f]);
+        }
+    }
+    ++next;
+  }
+  return comp;
+}
+
 int check_level(mg_ctx* c, int level, int need_coarser) {
   if (!c) return fail(MG_EINVAL, "null context");
   if (level < 0 || level >= c->L - need_coarser) return fail(MG_EINVAL, "level %d out of range", level);
@@ -469,7 +502,9 @@ int setup_impl(mg_ctx** out, void* workspace, size_t ws_bytes, const double* bx,
   c->active = cnt[1];
   c->dropped = cnt[2];
   coarse_dense(hbx, hby, hbz, hm, cl.n, cl.h, A);
-  mg::symmetric_pinv(nc, A, kPinvRtol, P);
+  // the null space is known exactly from the graph; eigendecomposition only as fallback
+  if (!mg::graph_pinv(nc, A, coarse_components(hbx, hby, hbz, hm, cl.n), 1e-14, P))
+    mg::symmetric_pinv(nc, A, kPinvRtol, P);
   hip(hipMemcpyAsync(c->pinv, P.data(), P.size() * sizeof(double), hipMemcpyHostToDevice, s), "upload pinv");
   hip(hipStreamSynchronize(s), "hipStreamSynchronize(pinv)");
   if (rc != MG_OK) return cleanup(rc);

@@ -173,6 +173,9 @@ __global__ __launch_bounds__(kBlock) void k_area_to_beta(const double* __restric
   if (az != 0.0) bz[c] = az * (2.0 / (rho[c] + rho[c - (1 << (2 * q))]));
 }
 
+// Close the finest faces (copy unless bx is null), validate them, mark active cells.
+// Grid-stride over cells with a bounded block count, so the three counters take few
+// atomic adds.
 __global__ __launch_bounds__(kBlock) void k_setup_fine(const double* __restrict__ ubx, const double* __restrict__ uby,
                                                        const double* __restrict__ ubz,
                                                        const uint8_t* __restrict__ umask, int q,
@@ -180,19 +183,17 @@ __global__ __launch_bounds__(kBlock) void k_setup_fine(const double* __restrict_
                                                        double* __restrict__ bz, uint8_t* __restrict__ mask,
                                                        long long* __restrict__ counters) {
   const int n = 1 << q, m = n - 1;
-  const long long t = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
-  const bool live = t < (1LL << (3 * q));
+  const int total = 1 << (3 * q);
+  const int nn = 1 << (2 * q);
   int bad = 0, active = 0, dropped = 0;
-  if (live) {
-    const int c = static_cast<int>(t);
+  for (int c = blockIdx.x * kBlock + threadIdx.x; c < total; c += gridDim.x * kBlock) {
     const int i = c & m, j = (c >> q) & m, k = c >> (2 * q);
     const bool mc = umask[c] != 0;
     const int cxm = cell((i - 1) & m, j, k, q), cxp = cell((i + 1) & m, j, k, q);
     const int cym = cell(i, (j - 1) & m, k, q), cyp = cell(i, (j + 1) & m, k, q);
-    const int nn = 1 << (2 * q);
     const double vx = ubx[c], vy = uby[c], vz = ubz[c];
-    bad = !(vx >= 0.0 && vx <= 1.7976931348623157e308) + !(vy >= 0.0 && vy <= 1.7976931348623157e308) +
-          !(vz >= 0.0 && vz <= 1.7976931348623157e308);
+    bad += !(vx >= 0.0 && vx <= 1.7976931348623157e308) + !(vy >= 0.0 && vy <= 1.7976931348623157e308) +
+           !(vz >= 0.0 && vz <= 1.7976931348623157e308);
     const double xm = (mc && umask[cxm]) ? vx : 0.0;
     const double ym = (mc && umask[cym]) ? vy : 0.0;
     const double zm = (k > 0 && mc && umask[c - nn]) ? vz : 0.0;
@@ -206,16 +207,22 @@ __global__ __launch_bounds__(kBlock) void k_setup_fine(const double* __restrict_
     }
     const bool act = mc && (xm + xp + ym + yp + zm + zp) > 0.0;
     mask[c] = act ? 1 : 0;
-    active = act;
-    dropped = mc && !act;
+    active += act;
+    dropped += mc && !act;
   }
-  const int nb = __syncthreads_count(bad);
-  const int na = __syncthreads_count(active);
-  const int nd = __syncthreads_count(dropped);
+  __shared__ int red[3][kBlock / 64];
+  int v[3] = {bad, active, dropped};
+  for (int x = 0; x < 3; ++x)
+    for (int off = 32; off > 0; off >>= 1) v[x] += __shfl_xor(v[x], off, 64);
+  if ((threadIdx.x & 63) == 0)
+    for (int x = 0; x < 3; ++x) red[x][threadIdx.x >> 6] = v[x];
+  __syncthreads();
   if (threadIdx.x == 0) {
-    if (nb) atomicAdd(reinterpret_cast<unsigned long long*>(&counters[0]), static_cast<unsigned long long>(nb));
-    if (na) atomicAdd(reinterpret_cast<unsigned long long*>(&counters[1]), static_cast<unsigned long long>(na));
-    if (nd) atomicAdd(reinterpret_cast<unsigned long long*>(&counters[2]), static_cast<unsigned long long>(nd));
+    for (int x = 0; x < 3; ++x) {
+      long long sum = 0;
+      for (int w = 0; w < kBlock / 64; ++w) sum += red[x][w];
+      if (sum) atomicAdd(reinterpret_cast<unsigned long long*>(&counters[x]), static_cast<unsigned long long>(sum));
+    }
   }
 }
 
@@ -646,8 +653,8 @@ hipError_t launch_coeffs_from_rho(const double* rho, const uint8_t* mask, int q,
 hipError_t launch_setup_fine(const double* ubx, const double* uby, const double* ubz, const uint8_t* umask, int q,
                              double* bx, double* by, double* bz, uint8_t* mask, long long* counters,
                              hipStream_t s) {
-  hipLaunchKernelGGL(k_setup_fine, dim3(grid_for(1LL << (3 * q))), dim3(kBlock), 0, s, ubx, uby, ubz, umask, q, bx,
-                     by, bz, mask, counters);
+  hipLaunchKernelGGL(k_setup_fine, dim3(reduction_blocks(1LL << (3 * q))), dim3(kBlock), 0, s, ubx, uby, ubz, umask, q,
+                     bx, by, bz, mask, counters);
   return hipGetLastError();
 }
 

@@ -7,6 +7,8 @@
 
 namespace mg {
 void symmetric_pinv(int n, std::vector<double>& a, double rtol, std::vector<double>& pinv);
+bool graph_pinv(int n, const std::vector<double>& a, const std::vector<int>& component, double rtol,
+                std::vector<double>& pinv);
 }
 
 static int failures = 0;
@@ -109,6 +111,20 @@ int main() {
   std::vector<double> d = {2, 0, 0, 0, 4, 0, 0, 0, 0};
   mg::symmetric_pinv(3, d, 1e-12, pinv);
   CHECK(std::abs(pinv[0] - 0.5) < 1e-15 && std::abs(pinv[4] - 0.25) < 1e-15 && pinv[8] == 0.0);
+  // graph pseudo-inverse: two components {0,1,2} and {3,4} plus an inactive cell 5
+  {
+    const int n = 6;
+    std::vector<double> g(n * n, 0.0);
+    auto edge = [&](int a, int b, double w) {
+      g[a * n + b] += w; g[b * n + a] += w; g[a * n + a] -= w; g[b * n + b] -= w;
+    };
+    edge(0, 1, 2.0); edge(1, 2, 1000.0); edge(0, 2, 0.5); edge(3, 4, 3.0);
+    std::vector<int> comp = {0, 0, 0, 1, 1, -1};
+    std::vector<double> pg, pj, gj = g;
+    CHECK(mg::graph_pinv(n, g, comp, 1e-14, pg));
+    mg::symmetric_pinv(n, gj, 1e-12, pj);
+    for (int i = 0; i < n * n; ++i) CHECK(std::abs(pg[i] - pj[i]) < 1e-12);
+  }
   std::printf("%s (%d failures)\n", failures ? "FAILED" : "OK", failures);
   return failures ? 1 : 0;
 }
