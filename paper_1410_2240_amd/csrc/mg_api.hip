@@ -152,8 +152,26 @@ int residual_restrict(mg_ctx* c, int l, const T* p, const T* f, const double* fs
 
 template <typename T>
 int vcycle(mg_ctx* c, int l, T* p, const T* f, const double* fshift) {
-  if (l == c->L - 1) {
-    MG_HIP(mg::launch_coarse_solve<T>(f, p, c->pinv, c->lv[l].mask, c->stream));
+  if (c->lv[l].n <= mg::kCoarseCycleMaxN) {
+    // grids of 16^3 and below: the rest of the cycle in one single-workgroup launch
+    mg::CoarseCycle<T> a{};
+    a.nlev = c->L - l;
+    for (int k = 0; k < a.nlev; ++k) {
+      const Level& lv = c->lv[l + k];
+      const View<T> v = c->view<T>(l + k);
+      a.q[k] = lv.q;
+      a.bx[k] = v.bx;
+      a.by[k] = v.by;
+      a.bz[k] = v.bz;
+      a.mask[k] = lv.mask;
+      a.f[k] = k == 0 ? const_cast<T*>(f) : v.f;
+      a.e[k] = k == 0 ? p : v.e;
+      a.h2[k] = static_cast<T>(lv.h * lv.h);
+      a.inv_h2[k] = static_cast<T>(1.0 / (lv.h * lv.h));
+    }
+    a.pinv = c->pinv;
+    a.fshift = fshift;
+    MG_HIP(mg::launch_coarse_cycle<T>(a, c->stream));
     return MG_OK;
   }
   const View<T> next = c->view<T>(l + 1);

@@ -330,9 +330,10 @@ hipError_t launch_tx(const T* pin, T* pout, const T* f, const T* bx, const T* by
   const int n = 1 << q;
   constexpr int threads = TX / 2 * kTY;
   const long long tiles = static_cast<long long>(n / TX) * (n / kTY);
-  // z-chunk: as long as possible (overlap planes per chunk) while still giving at least
-  // one 1024-thread workgroup per compute unit
-  const long long want = 256LL * 1024 / threads;
+  // z-chunk: as long as possible (overlap planes per chunk) while still giving each
+  // compute unit the workgroups it can hold at once (FP64 needs about twice the
+  // registers of FP32, so half as many fit)
+  const long long want = 256LL * 1024 / threads / (sizeof(T) == 8 ? 2 : 1);
   int kc = 32;
   while (kc > 4 && tiles * (n / kc) < want) kc /= 2;
   if (kc > n) kc = n;

@@ -47,6 +47,28 @@ hipError_t launch_prolong_add(const T* ec, T* p, const uint8_t* mask, int q, hip
 template <typename T>
 hipError_t launch_coarse_solve(const T* f, T* e, const double* pinv, const uint8_t* mask, hipStream_t s);
 
+// Levels of the single-workgroup sub-cycle: entry 0 is the first grid it handles
+// (at most 16^3), the last entry the 4^3 grid.  e[0] must be zero on entry (or hold
+// the guess), f[0] the right-hand side; fshift applies to level 0 only.
+constexpr int kCoarseCycleMaxN = 16;
+template <typename T>
+struct CoarseCycle {
+  int nlev;
+  int q[4];
+  const T* bx[4];
+  const T* by[4];
+  const T* bz[4];
+  const uint8_t* mask[4];
+  T* f[4];
+  T* e[4];
+  T h2[4];
+  T inv_h2[4];
+  const double* pinv;
+  const double* fshift;
+};
+template <typename T>
+hipError_t launch_coarse_cycle(const CoarseCycle<T>& a, hipStream_t s);
+
 // ---- FP64 finest-grid passes ------------------------------------------------------
 // partials[blockIdx] = sum over active cells of r^2, r = (f - fshift) - A p; optional
 // r32 = float(r) and e32 = 0 (mixed-precision refinement); returns the block count used.

@@ -274,40 +274,43 @@ __global__ __launch_bounds__(kBlock) void k_to_f32(const double* __restrict__ sr
 // the other colour, so the update order inside the launch does not matter.
 // One thread per pair of x-neighbours (one cell of each colour).
 template <typename T>
+__device__ __forceinline__ void gs_pair(T* __restrict__ p, const T* __restrict__ f, const T* __restrict__ bx,
+                                        const T* __restrict__ by, const T* __restrict__ bz, int q, T h2, int colour,
+                                        T fs, int pr) {
+  const int m = (1 << q) - 1;
+  const int ip = pr & (m >> 1), j = (pr >> (q - 1)) & m, k = pr >> (2 * q - 1);
+  const int i = 2 * ip + ((colour + j + k) & 1);
+  const Faces<T> F = load_faces(bx, by, bz, i, j, k, q);
+  const int c = cell(i, j, k, q);
+  // every load issued before the activity test, so they are in flight together
+  const T pxm = p[F.cxm], pxp = p[F.cxp], pym = p[F.cym], pyp = p[F.cyp], pzm = p[F.czm], pzp = p[F.czp];
+  const T fc = f[c];
+  const T D = diag(F);
+  if (!(D > T(0))) return;
+  const T S = F.xm * pxm + F.xp * pxp + F.ym * pym + F.yp * pyp + F.zm * pzm + F.zp * pzp;
+  p[c] = (S - h2 * (fc - fs)) / D;
+}
+
+template <typename T>
 __global__ __launch_bounds__(kBlock) void k_rbgs_half(T* __restrict__ p, const T* __restrict__ f,
                                                       const T* __restrict__ bx, const T* __restrict__ by,
                                                       const T* __restrict__ bz, int q, T h2, int colour,
                                                       const double* __restrict__ fshift) {
-  const int m = (1 << q) - 1;
   const long long t = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
   if (t >= (1LL << (3 * q - 1))) return;
-  const int pr = static_cast<int>(t);
-  const int ip = pr & (m >> 1), j = (pr >> (q - 1)) & m, k = pr >> (2 * q - 1);
-  const int i = 2 * ip + ((colour + j + k) & 1);
-  const Faces<T> F = load_faces(bx, by, bz, i, j, k, q);
-  const T D = diag(F);
-  if (!(D > T(0))) return;
-  const int c = cell(i, j, k, q);
   const T fs = fshift ? static_cast<T>(*fshift) : T(0);
-  const T S = F.xm * p[F.cxm] + F.xp * p[F.cxp] + F.ym * p[F.cym] + F.yp * p[F.cyp] + F.zm * p[F.czm] +
-              F.zp * p[F.czp];
-  p[c] = (S - h2 * (f[c] - fs)) / D;
+  gs_pair(p, f, bx, by, bz, q, h2, colour, fs, static_cast<int>(t));
 }
 
 // fc = mean over the 8 children of r = (f - fshift) - A p; ec = 0.  One thread per
 // coarse cell: its children are two x-pairs on each of two rows and two planes.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_residual_restrict(const T* __restrict__ p, const T* __restrict__ f,
-                                                              const T* __restrict__ bx, const T* __restrict__ by,
-                                                              const T* __restrict__ bz, int q, T inv_h2,
-                                                              const double* __restrict__ fshift,
-                                                              T* __restrict__ fc, T* __restrict__ ec) {
+__device__ __forceinline__ void restrict_cell(const T* __restrict__ p, const T* __restrict__ f,
+                                              const T* __restrict__ bx, const T* __restrict__ by,
+                                              const T* __restrict__ bz, int q, T inv_h2, T fs, T* __restrict__ fc,
+                                              T* __restrict__ ec, int C) {
   const int qc = q - 1, mc = (1 << qc) - 1;
-  const long long t = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
-  if (t >= (1LL << (3 * qc))) return;
-  const int C = static_cast<int>(t);
   const int I = C & mc, J = (C >> qc) & mc, K = C >> (2 * qc);
-  const T fs = fshift ? static_cast<T>(*fshift) : T(0);
   T sum = T(0);
 #pragma unroll
   for (int d = 0; d < 4; ++d) {
@@ -319,18 +322,27 @@ __global__ __launch_bounds__(kBlock) void k_residual_restrict(const T* __restric
   ec[C] = T(0);
 }
 
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_residual_restrict(const T* __restrict__ p, const T* __restrict__ f,
+                                                              const T* __restrict__ bx, const T* __restrict__ by,
+                                                              const T* __restrict__ bz, int q, T inv_h2,
+                                                              const double* __restrict__ fshift,
+                                                              T* __restrict__ fc, T* __restrict__ ec) {
+  const long long t = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
+  if (t >= (1LL << (3 * (q - 1)))) return;
+  const T fs = fshift ? static_cast<T>(*fshift) : T(0);
+  restrict_cell(p, f, bx, by, bz, q, inv_h2, fs, fc, ec, static_cast<int>(t));
+}
+
 // p += mask * trilinear(ec); 1-D weights 3/4 (parent) and 1/4 (nearer neighbour),
 // periodic in x and y, parent reused for a z neighbour outside the grid.  One thread
 // per coarse cell updates its 8 children (x-pairs on two rows of two planes), applying
 // the 1-D weights in x, then y, then z.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_prolong_add(const T* __restrict__ ec, T* __restrict__ p,
-                                                        const uint8_t* __restrict__ mask, int q) {
+__device__ __forceinline__ void prolong_cell(const T* __restrict__ ec, T* __restrict__ p,
+                                             const uint8_t* __restrict__ mask, int q, int C) {
   using V2 = typename V2of<T>::type;
   const int qc = q - 1, mc = (1 << qc) - 1;
-  const long long t = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
-  if (t >= (1LL << (3 * qc))) return;
-  const int C = static_cast<int>(t);
   const int I = C & mc, J = (C >> qc) & mc, K = C >> (2 * qc);
   const int Ix[3] = {(I - 1) & mc, I, (I + 1) & mc};
   const int Jy[3] = {(J - 1) & mc, J, (J + 1) & mc};
@@ -370,26 +382,96 @@ __global__ __launch_bounds__(kBlock) void k_prolong_add(const T* __restrict__ ec
     }
 }
 
-// e = A_c^+ (f - active mean of f) on the 4^3 grid, in FP64; one wavefront of 64 lanes.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_prolong_add(const T* __restrict__ ec, T* __restrict__ p,
+                                                        const uint8_t* __restrict__ mask, int q) {
+  const long long t = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
+  if (t >= (1LL << (3 * (q - 1)))) return;
+  prolong_cell(ec, p, mask, q, static_cast<int>(t));
+}
+
+// e = A_c^+ (f - active mean of f) on the 4^3 grid, in FP64, by the first wavefront
+// (64 lanes) of the calling block; fh is a 64-double shared buffer.
+template <typename T>
+__device__ __forceinline__ void coarse_solve_wave(const T* __restrict__ f, T* __restrict__ e,
+                                                  const double* __restrict__ pinv, const uint8_t* __restrict__ mask,
+                                                  double* fh) {
+  const int t = threadIdx.x;
+  if (t < 64) {
+    const bool act = mask[t] != 0;
+    const double v = act ? static_cast<double>(f[t]) : 0.0;
+    double s = v, cnt = act ? 1.0 : 0.0;
+    for (int off = 32; off > 0; off >>= 1) {
+      s += __shfl_xor(s, off, 64);
+      cnt += __shfl_xor(cnt, off, 64);
+    }
+    const double mean = cnt > 0.0 ? s / cnt : 0.0;
+    fh[t] = act ? v - mean : 0.0;
+  }
+  __syncthreads();
+  if (t < 64) {
+    double acc = 0.0;
+    for (int c = 0; c < 64; ++c) acc += pinv[t * 64 + c] * fh[c];
+    e[t] = static_cast<T>(acc);
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(64) void k_coarse_solve(const T* __restrict__ f, T* __restrict__ e,
                                                      const double* __restrict__ pinv,
                                                      const uint8_t* __restrict__ mask) {
   __shared__ double fh[64];
-  const int t = threadIdx.x;
-  const bool act = mask[t] != 0;
-  double v = act ? static_cast<double>(f[t]) : 0.0;
-  double s = v, cnt = act ? 1.0 : 0.0;
-  for (int off = 32; off > 0; off >>= 1) {
-    s += __shfl_xor(s, off, 64);
-    cnt += __shfl_xor(cnt, off, 64);
+  coarse_solve_wave(f, e, pinv, mask, fh);
+}
+
+// The whole V(2,2) sub-cycle on grids of 16^3 and smaller, by one workgroup: the same
+// per-cell steps as the multi-block kernels, separated by workgroup barriers instead of
+// kernel launches.  Level 0 of `a` enters with its right-hand side and a zero correction.
+// The level loops are unrolled over the at most three grids (16^3, 8^3, 4^3) so every
+// field of `a` is read with a constant index.
+constexpr int kCoarseThreads = 512;
+
+template <typename T>
+__global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle(CoarseCycle<T> a) {
+  __shared__ double fh[64];
+  const int tid = threadIdx.x;
+  const int last = a.nlev - 1;
+  auto sweep = [&](int l, int colour) {
+    const T fs = (l == 0 && a.fshift) ? static_cast<T>(*a.fshift) : T(0);
+    for (int pr = tid; pr < (1 << (3 * a.q[l] - 1)); pr += kCoarseThreads)
+      gs_pair(a.e[l], a.f[l], a.bx[l], a.by[l], a.bz[l], a.q[l], a.h2[l], colour, fs, pr);
+    __syncthreads();
+  };
+#pragma unroll
+  for (int l = 0; l < 2; ++l) {
+    if (l < last) {
+      for (int s = 0; s < 2; ++s) {
+        sweep(l, 0);
+        sweep(l, 1);
+      }
+      const T fs = (l == 0 && a.fshift) ? static_cast<T>(*a.fshift) : T(0);
+      for (int C = tid; C < (1 << (3 * (a.q[l] - 1))); C += kCoarseThreads)
+        restrict_cell(a.e[l], a.f[l], a.bx[l], a.by[l], a.bz[l], a.q[l], a.inv_h2[l], fs, a.f[l + 1], a.e[l + 1], C);
+      __syncthreads();
+    }
   }
-  const double mean = cnt > 0.0 ? s / cnt : 0.0;
-  fh[t] = act ? v - mean : 0.0;
+  const T* fl = last == 0 ? a.f[0] : (last == 1 ? a.f[1] : a.f[2]);
+  T* el = last == 0 ? a.e[0] : (last == 1 ? a.e[1] : a.e[2]);
+  const uint8_t* ml = last == 0 ? a.mask[0] : (last == 1 ? a.mask[1] : a.mask[2]);
+  coarse_solve_wave(fl, el, a.pinv, ml, fh);
   __syncthreads();
-  double acc = 0.0;
-  for (int c = 0; c < 64; ++c) acc += pinv[t * 64 + c] * fh[c];
-  e[t] = static_cast<T>(acc);
+#pragma unroll
+  for (int l = 1; l >= 0; --l) {
+    if (l < last) {
+      for (int C = tid; C < (1 << (3 * (a.q[l] - 1))); C += kCoarseThreads)
+        prolong_cell(a.e[l + 1], a.e[l], a.mask[l], a.q[l], C);
+      __syncthreads();
+      for (int s = 0; s < 2; ++s) {
+        sweep(l, 1);
+        sweep(l, 0);
+      }
+    }
+  }
 }
 
 // ------------------------------------------------------------------ FP64 finest passes
@@ -792,13 +874,21 @@ hipError_t launch_fcg_dir(const double* z64, const float* z32, double* d, const 
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_coarse_cycle(const CoarseCycle<T>& a, hipStream_t s) {
+  if (a.nlev < 1 || a.nlev > 3) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_coarse_cycle<T>, dim3(1), dim3(kCoarseThreads), 0, s, a);
+  return hipGetLastError();
+}
+
 #define MG_INSTANTIATE(T)                                                                                        \
   template hipError_t launch_rbgs_half<T>(T*, const T*, const T*, const T*, const T*, int, double, int,          \
                                           const double*, hipStream_t);                                           \
   template hipError_t launch_residual_restrict<T>(const T*, const T*, const T*, const T*, const T*, int, double, \
                                                   const double*, T*, T*, hipStream_t);                           \
   template hipError_t launch_prolong_add<T>(const T*, T*, const uint8_t*, int, hipStream_t);                     \
-  template hipError_t launch_coarse_solve<T>(const T*, T*, const double*, const uint8_t*, hipStream_t);
+  template hipError_t launch_coarse_solve<T>(const T*, T*, const double*, const uint8_t*, hipStream_t);    \
+  template hipError_t launch_coarse_cycle<T>(const CoarseCycle<T>&, hipStream_t);
 MG_INSTANTIATE(double)
 MG_INSTANTIATE(float)
 #undef MG_INSTANTIATE
