@@ -160,6 +160,22 @@ int mg_apply(mg_ctx* ctx, const double* p, double* Ap, int batch);
 int mg_coeff_grad(mg_ctx* ctx, const double* mu, const double* p, int batch,
                   double* gbx, double* gby, double* gbz, double* grho);
 
+/*
+ * The Runge-Kutta stage around the solve (section 2.1, eqs. (poisson1) / (poisson2) and
+ * (runge1) / (runge2), in the finite-volume form of eq. (integral2)).  Velocities are
+ * the normal components on the faces, in the low-face storage of the coefficients
+ * (ux[k][j][i] on the face between (i-1, j, k) and (i, j, k), ...).  A face is open when
+ * both cells are active and it is not a z wall; R (the non-pressure terms) may be NULL.
+ *   mg_divergence:  f_c = (1/h) sum_faces (+-)(U_f + dt R_f) / dt on active cells, else 0
+ *   mg_project:     U_f <- U_f + dt R_f - dt beta_f (p_hi - p_lo) / h on open faces, 0 on
+ *                   closed ones (a body at rest), in place
+ * With A p = f solved, the projected field has zero discrete divergence.  dt > 0.
+ */
+int mg_divergence(mg_ctx* ctx, const double* ux, const double* uy, const double* uz,
+                  const double* rx, const double* ry, const double* rz, double dt, double* f);
+int mg_project(mg_ctx* ctx, double* ux, double* uy, double* uz,
+               const double* rx, const double* ry, const double* rz, double dt, const double* p);
+
 void mg_destroy(mg_ctx* ctx);
 
 /* Thread-local message describing the last failure on this thread ("" if none). */

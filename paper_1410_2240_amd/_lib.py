@@ -45,6 +45,8 @@ SIGNATURES = {
     "mg_solve": (_I, [_P, _P, _P, _I, _D, _I, ctypes.POINTER(_D), ctypes.POINTER(_I), ctypes.POINTER(MgStats)]),
     "mg_apply": (_I, [_P, _P, _P, _I]),
     "mg_coeff_grad": (_I, [_P, _P, _P, _I, _P, _P, _P, _P]),
+    "mg_divergence": (_I, [_P, _P, _P, _P, _P, _P, _P, _D, _P]),
+    "mg_project": (_I, [_P, _P, _P, _P, _P, _P, _P, _D, _P]),
     "mg_destroy": (None, [_P]),
     "mg_last_error": (ctypes.c_char_p, []),
     "mg_level_info": (_I, [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_D)]),

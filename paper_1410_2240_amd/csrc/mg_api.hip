@@ -627,6 +627,28 @@ int mg_coeff_grad(mg_ctx* ctx, const double* mu, const double* p, int batch, dou
   return MG_OK;
 }
 
+int mg_divergence(mg_ctx* ctx, const double* ux, const double* uy, const double* uz, const double* rx,
+                  const double* ry, const double* rz, double dt, double* f) {
+  if (!ctx) return fail(MG_EINVAL, "null context");
+  if (!ux || !uy || !uz || !f) return fail(MG_EINVAL, "null array pointer");
+  if ((rx || ry || rz) && !(rx && ry && rz)) return fail(MG_EINVAL, "give all three R components or none");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(MG_EINVAL, "dt must be positive and finite");
+  const Level& a = ctx->lv[0];
+  MG_HIP(mg::launch_divergence(ux, uy, uz, rx, ry, rz, dt, a.mask, a.q, a.h, f, ctx->stream));
+  return MG_OK;
+}
+
+int mg_project(mg_ctx* ctx, double* ux, double* uy, double* uz, const double* rx, const double* ry, const double* rz,
+               double dt, const double* p) {
+  if (!ctx) return fail(MG_EINVAL, "null context");
+  if (!ux || !uy || !uz || !p) return fail(MG_EINVAL, "null array pointer");
+  if ((rx || ry || rz) && !(rx && ry && rz)) return fail(MG_EINVAL, "give all three R components or none");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(MG_EINVAL, "dt must be positive and finite");
+  const Level& a = ctx->lv[0];
+  MG_HIP(mg::launch_project(ux, uy, uz, rx, ry, rz, dt, p, a.bx, a.by, a.bz, a.mask, a.q, a.h, ctx->stream));
+  return MG_OK;
+}
+
 void mg_destroy(mg_ctx* ctx) {
   if (!ctx) return;
   if (ctx->host) (void)hipHostFree(ctx->host);

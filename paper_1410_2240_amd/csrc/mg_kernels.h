@@ -103,4 +103,13 @@ hipError_t launch_coeff_grad(const double* mu, const double* p, int batch, const
                              const double* by, const double* bz, const uint8_t* mask, int q, double h,
                              double* gbx, double* gby, double* gbz, double* grho, hipStream_t s);
 
+// Runge-Kutta stage around the solve: f = div(U + dt R)/dt, and the projection
+// U <- o_f (U + dt R - dt beta grad p) on the faces (R may be null)
+hipError_t launch_divergence(const double* ux, const double* uy, const double* uz, const double* rx, const double* ry,
+                             const double* rz, double dt, const uint8_t* mask, int q, double h, double* f,
+                             hipStream_t s);
+hipError_t launch_project(double* ux, double* uy, double* uz, const double* rx, const double* ry, const double* rz,
+                          double dt, const double* p, const double* bx, const double* by, const double* bz,
+                          const uint8_t* mask, int q, double h, hipStream_t s);
+
 }  // namespace mg

@@ -717,6 +717,62 @@ __global__ __launch_bounds__(kBlock) void k_fcg_dir(const double* __restrict__ z
   *reinterpret_cast<double2*>(d + c) = double2{zv.x + beta * dv.x, zv.y + beta * dv.y};
 }
 
+// ------------------------------------------- Runge-Kutta stage around the solve (FP64)
+// Face velocities use the low-face storage of the face coefficients.  A face is open
+// when both cells are active (and it is not a z wall); closed faces carry no flux.
+
+// f_c = div(U + dt R)_c / dt on active cells (R may be null)
+__global__ __launch_bounds__(kBlock) void k_divergence(const double* __restrict__ ux, const double* __restrict__ uy,
+                                                       const double* __restrict__ uz, const double* __restrict__ rx,
+                                                       const double* __restrict__ ry, const double* __restrict__ rz,
+                                                       double dt, const uint8_t* __restrict__ mask, int q,
+                                                       double inv_hdt, double* __restrict__ f) {
+  const int n = 1 << q, m = n - 1, nn = 1 << (2 * q);
+  const long long t = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
+  if (t >= (1LL << (3 * q))) return;
+  const int c = static_cast<int>(t);
+  const int i = c & m, j = (c >> q) & m, k = c >> (2 * q);
+  if (!mask[c]) {
+    f[c] = 0.0;
+    return;
+  }
+  const int cxp = cell((i + 1) & m, j, k, q), cxm = cell((i - 1) & m, j, k, q);
+  const int cyp = cell(i, (j + 1) & m, k, q), cym = cell(i, (j - 1) & m, k, q);
+  auto U = [&](const double* a, const double* r, int at) { return r ? a[at] + dt * r[at] : a[at]; };
+  double div = 0.0;
+  if (mask[cxp]) div += U(ux, rx, cxp);
+  if (mask[cxm]) div -= U(ux, rx, c);
+  if (mask[cyp]) div += U(uy, ry, cyp);
+  if (mask[cym]) div -= U(uy, ry, c);
+  if (k < m && mask[c + nn]) div += U(uz, rz, c + nn);
+  if (k > 0 && mask[c - nn]) div -= U(uz, rz, c);
+  f[c] = div * inv_hdt;
+}
+
+// U_f <- o_f (U_f + dt R_f - dt beta_f (p_hi - p_lo) / h) on the low faces of each cell
+__global__ __launch_bounds__(kBlock) void k_project(double* __restrict__ ux, double* __restrict__ uy,
+                                                    double* __restrict__ uz, const double* __restrict__ rx,
+                                                    const double* __restrict__ ry, const double* __restrict__ rz,
+                                                    double dt, const double* __restrict__ p,
+                                                    const double* __restrict__ bx, const double* __restrict__ by,
+                                                    const double* __restrict__ bz, const uint8_t* __restrict__ mask,
+                                                    int q, double dt_over_h) {
+  const int n = 1 << q, m = n - 1, nn = 1 << (2 * q);
+  const long long t = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
+  if (t >= (1LL << (3 * q))) return;
+  const int c = static_cast<int>(t);
+  const int i = c & m, j = (c >> q) & m, k = c >> (2 * q);
+  const bool mc = mask[c] != 0;
+  const int cxm = cell((i - 1) & m, j, k, q), cym = cell(i, (j - 1) & m, k, q);
+  const double pc = p[c];
+  auto upd = [&](double* a, const double* r, const double* b, int lo, bool open) {
+    a[c] = open ? (r ? a[c] + dt * r[c] : a[c]) - dt_over_h * b[c] * (pc - p[lo]) : 0.0;
+  };
+  upd(ux, rx, bx, cxm, mc && mask[cxm]);
+  upd(uy, ry, by, cym, mc && mask[cym]);
+  upd(uz, rz, bz, k > 0 ? c - nn : c, k > 0 && mc && mask[c - nn]);
+}
+
 int reduction_blocks(long long work) {
   long long b = (work + kBlock - 1) / kBlock;
   return static_cast<int>(b < kNumPartials ? b : kNumPartials);
@@ -878,6 +934,22 @@ template <typename T>
 hipError_t launch_coarse_cycle(const CoarseCycle<T>& a, hipStream_t s) {
   if (a.nlev < 1 || a.nlev > 3) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_coarse_cycle<T>, dim3(1), dim3(kCoarseThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_divergence(const double* ux, const double* uy, const double* uz, const double* rx, const double* ry,
+                             const double* rz, double dt, const uint8_t* mask, int q, double h, double* f,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_divergence, dim3(grid_for(1LL << (3 * q))), dim3(kBlock), 0, s, ux, uy, uz, rx, ry, rz, dt, mask,
+                     q, 1.0 / (h * dt), f);
+  return hipGetLastError();
+}
+
+hipError_t launch_project(double* ux, double* uy, double* uz, const double* rx, const double* ry, const double* rz,
+                          double dt, const double* p, const double* bx, const double* by, const double* bz,
+                          const uint8_t* mask, int q, double h, hipStream_t s) {
+  hipLaunchKernelGGL(k_project, dim3(grid_for(1LL << (3 * q))), dim3(kBlock), 0, s, ux, uy, uz, rx, ry, rz, dt, p, bx,
+                     by, bz, mask, q, dt / h);
   return hipGetLastError();
 }
 

@@ -164,6 +164,26 @@ class MG:
                                          _ptr(g[0]), _ptr(g[1]), _ptr(g[2]), _ptr(grho)), "mg_coeff_grad")
         return (grho, tuple(g)) if faces else grho
 
+    # ---------------------------------------------------------------- Runge-Kutta stage
+
+    def divergence(self, u, r=None, dt: float = 1.0):
+        """f = div(U + dt R) / dt from face velocities u = (ux, uy, uz) (and R)."""
+        self._sync_stream()
+        f = torch.empty_like(u[0])
+        rr = (None, None, None) if r is None else r
+        _check(_lib.load().mg_divergence(self._ctx, *(_ptr(t, torch.float64) for t in u),
+                                         *(_ptr(t, torch.float64) for t in rr), float(dt), _ptr(f)), "mg_divergence")
+        return f
+
+    def project(self, u, p, r=None, dt: float = 1.0):
+        """u <- u + dt R - dt beta grad p on open faces, 0 on closed ones (in place)."""
+        self._sync_stream()
+        rr = (None, None, None) if r is None else r
+        _check(_lib.load().mg_project(self._ctx, *(_ptr(t, torch.float64) for t in u),
+                                      *(_ptr(t, torch.float64) for t in rr), float(dt), _ptr(p, torch.float64)),
+               "mg_project")
+        return u
+
     # ---------------------------------------------------------------- components
 
     def level_info(self, level: int):

@@ -263,3 +263,42 @@ def test_face_product_coarsening_beats_density_coarsening(name):
     plain = MG.from_rho(dev(inp.rho), dev(inp.mask), coarsening="density")
     _, hp, st = plain.solve(dev(inp.f), tol=1e-10, max_cycles=40, raise_on_fail=False)
     assert st["status"] in (MG_EBREAKDOWN, MG_ENOCONV) and hp[-1] > 1e-6
+
+
+# ------------------------------------------------------------------ Runge-Kutta stage around the solve
+
+def test_divergence_and_projection_match_oracle():
+    from oracle import projection
+    from paper_1410_2240_amd import MG
+    from tests.gpu_helpers import maxrel
+    inp, H = workload("c2", 32)
+    g = np.random.default_rng(140)
+    U = tuple(g.standard_normal((32, 32, 32)) for _ in range(3))
+    R = tuple(g.standard_normal((32, 32, 32)) for _ in range(3))
+    p = np.where(H.fine.mask, g.standard_normal((32, 32, 32)), 0.0)
+    mg = MG.from_rho(dev(inp.rho), dev(inp.mask))
+    dt = 0.02
+    for r in (None, R):
+        f = host(mg.divergence(tuple(dev(a) for a in U), None if r is None else tuple(dev(a) for a in r), dt))
+        assert maxrel(f, projection.divergence(U, H.fine, dt, r)) <= 1e-13
+        ud = tuple(dev(a) for a in U)
+        mg.project(ud, dev(p), None if r is None else tuple(dev(a) for a in r), dt)
+        for got, want in zip(ud, projection.project(U, p, H.fine, dt, r)):
+            assert maxrel(host(got), want) <= 1e-13
+
+
+def test_runge_kutta_stage_leaves_no_divergence_256():
+    """f = div(U + dt R)/dt, flexible-CG solve to 1e-12, projection: the new face
+    velocity is discretely divergence-free at the bench size (oracle-free property)."""
+    from paper_1410_2240_amd import MG
+    inp, _ = workload("c2", 256)
+    mg = MG.from_rho(dev(inp.rho), dev(inp.mask), krylov=True)
+    g = torch.Generator(device="cuda").manual_seed(7)
+    U = tuple(torch.randn((256, 256, 256), dtype=torch.float64, device="cuda", generator=g) for _ in range(3))
+    R = tuple(torch.randn((256, 256, 256), dtype=torch.float64, device="cuda", generator=g) for _ in range(3))
+    dt = 1e-3
+    f = mg.divergence(U, R, dt)
+    p, hist, st = mg.solve(f, tol=1e-12, max_cycles=60)
+    mg.project(U, p, R, dt)
+    d = mg.divergence(U, None, 1.0)
+    assert float(d.abs().max()) <= 1e-9 * float(f.abs().max()) * dt * 10
