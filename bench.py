@@ -20,6 +20,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# Algorithmic scalars moved per finest cell by one V(2,2) cycle.  A grid with the face
+# arrays: 4 sweeps x 6 (p, f, bx, by, bz read, p written) + residual-and-restrict 5.125
+# + prolongation 2.125 = 31.25, and each coarser grid 1/8 of the one above.  The FP64
+# finest grid of a hierarchy built from rho reads one density instead of three face
+# arrays: 4 x 4 + 3.125 + 2.125 = 21.25, plus 31.25 / 7 for the coarser grids.
+VCYCLE_SCALARS_F32 = 31.25 * 8 / 7
+VCYCLE_SCALARS_F64 = 21.25 + 31.25 / 7
 
 
 def parse():
@@ -124,8 +131,9 @@ def main():
     b.record()
     torch.cuda.synchronize()
     launch_ms = a.elapsed_time(b) / (2 * reps)
-    # algorithmic bytes of one red-black sweep: p, f and three face arrays read, p written
-    half_bytes = n * 8 * 6
+    # algorithmic bytes of one red-black sweep on the finest grid of a hierarchy built
+    # from rho: p, f and the density form of the coefficients read, p written
+    half_bytes = n * 8 * 4
     achieved = half_bytes / (launch_ms * 1e-3) / 1e9
     del mg64, p64, fz, ps
     torch.cuda.empty_cache()
@@ -182,9 +190,12 @@ def main():
         "coarsening_ablation": abl,
         "vcycle_ms": {"fp64": vc64, "fp32": vc32},
         "vcycle_pts_per_s": {"fp64": n / (vc64 * 1e-3), "fp32": n / (vc32 * 1e-3)},
-        "vcycle_roofline_frac": {"fp64": 35.7 * 8 * n / (vc64 * 1e-3) / (HBM_PEAK_GBS * 1e9),
-                                 "fp32": 35.7 * 4 * n / (vc32 * 1e-3) / (HBM_PEAK_GBS * 1e9)},
-        "roofline": {"bound": "hbm", "kernel": "rbgs_fused (finest grid, FP64, one red-black sweep)", "achieved": achieved,
+        # algorithmic scalars per finest cell per V(2,2) cycle: the FP64 finest grid reads
+        # the density form (4 sweeps x 4 + 3.125 + 2.125), FP32 grids the face arrays
+        "vcycle_roofline_frac": {"fp64": VCYCLE_SCALARS_F64 * 8 * n / (vc64 * 1e-3) / (HBM_PEAK_GBS * 1e9),
+                                 "fp32": VCYCLE_SCALARS_F32 * 4 * n / (vc32 * 1e-3) / (HBM_PEAK_GBS * 1e9)},
+        "roofline": {"bound": "hbm", "kernel": "rbgs_fused (finest grid, FP64 density form, one red-black sweep)",
+                     "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "launch_ms": launch_ms, "bytes_per_launch": half_bytes},
         "input_gen_s": t_gen,

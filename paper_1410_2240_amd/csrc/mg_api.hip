@@ -60,6 +60,7 @@ struct Level {
   int n = 0, q = 0;
   double h = 0;
   double *bx = nullptr, *by = nullptr, *bz = nullptr, *f = nullptr, *e = nullptr, *t = nullptr;
+  double* rt = nullptr;   // finest grid of a hierarchy built from rho: the density form
   uint8_t* mask = nullptr;
   float *bx32 = nullptr, *by32 = nullptr, *bz32 = nullptr, *f32 = nullptr, *e32 = nullptr, *t32 = nullptr;
 };
@@ -67,6 +68,7 @@ struct Level {
 template <typename T>
 struct View {
   T *bx, *by, *bz, *f, *e, *t;
+  const T* rt;   // density form of the coefficients (FP64 finest grid only), else null
 };
 
 }  // namespace
@@ -88,11 +90,11 @@ struct mg_ctx {
 
   View<double> v64(int l) const {
     const Level& a = lv[l];
-    return {a.bx, a.by, a.bz, a.f, a.e, a.t};
+    return {a.bx, a.by, a.bz, a.f, a.e, a.t, a.rt};
   }
   View<float> v32(int l) const {
     const Level& a = lv[l];
-    return {a.bx32, a.by32, a.bz32, a.f32, a.e32, a.t32};
+    return {a.bx32, a.by32, a.bz32, a.f32, a.e32, a.t32, nullptr};
   }
   template <typename T>
   View<T> view(int l) const;
@@ -125,7 +127,7 @@ int smooth(mg_ctx* c, int l, T* p, const T* f, const double* fshift, int sweeps,
     T* src = p;
     T* dst = v.t;
     for (int s = 0; s < sweeps; ++s) {
-      MG_HIP(mg::launch_rbgs_fused<T>(src, dst, f, v.bx, v.by, v.bz, a.q, a.h, order, fshift, c->stream));
+      MG_HIP(mg::launch_rbgs_fused<T>(src, dst, f, v.bx, v.by, v.bz, v.rt, a.q, a.h, order, fshift, c->stream));
       T* tmp = src;
       src = dst;
       dst = tmp;
@@ -146,7 +148,7 @@ template <typename T>
 int residual_restrict(mg_ctx* c, int l, const T* p, const T* f, const double* fshift, T* fc, T* ec) {
   const Level& a = c->lv[l];
   const View<T> v = c->view<T>(l);
-  MG_HIP(mg::launch_residual_restrict<T>(p, f, v.bx, v.by, v.bz, a.q, a.h, fshift, fc, ec, c->stream));
+  MG_HIP(mg::launch_residual_restrict<T>(p, f, v.bx, v.by, v.bz, v.rt, a.q, a.h, fshift, fc, ec, c->stream));
   return MG_OK;
 }
 
@@ -203,7 +205,7 @@ int residual_norm(mg_ctx* c, const double* p, const double* f, const double* fsh
                   double* r64 = nullptr, double* z64 = nullptr) {
   const Level& a = c->lv[0];
   int nb = 0;
-  MG_HIP(mg::launch_residual_norm(p, f, a.bx, a.by, a.bz, a.q, a.h, fshift, r32, e32, r64, z64, c->partials, &nb,
+  MG_HIP(mg::launch_residual_norm(p, f, a.bx, a.by, a.bz, a.rt, a.q, a.h, fshift, r32, e32, r64, z64, c->partials, &nb,
                                   c->stream));
   return reduce(c, nb, 1.0, S_RNORM2);
 }
@@ -275,7 +277,7 @@ int solve_one(mg_ctx* c, const double* f, double* p, double tol, int max_cycles,
     }
     while (std::isfinite(r) && r > tol && *cycles < max_cycles) {
       int nb = 0;
-      MG_HIP(mg::launch_fcg_aw(kd, kr, a.bx, a.by, a.bz, q, a.h, kw, part(c, 0), part(c, 1), &nb, c->stream));
+      MG_HIP(mg::launch_fcg_aw(kd, kr, a.bx, a.by, a.bz, a.rt, q, a.h, kw, part(c, 0), part(c, 1), &nb, c->stream));
       MG_TRY(reduce_set(c, 0, nb, S_DW));
       MG_TRY(reduce_set(c, 1, nb, S_DR));
       MG_HIP(mg::launch_fcg_update(p, kr, kd, kw, c->scal + S_DR, c->scal + S_DW, q, mixed ? nullptr : kz,
@@ -474,6 +476,12 @@ int setup_impl(mg_ctx** out, void* workspace, size_t ws_bytes, const double* bx,
         "setup_fine");
   } else {
     hip(mg::launch_setup_fine(bx, by, bz, mask, f0.q, f0.bx, f0.by, f0.bz, f0.mask, c->counters, s), "setup_fine");
+  }
+  if (rho) {
+    // density form of the finest coefficients, read by the finest-grid passes in place
+    // of the three face arrays
+    f0.rt = at<double>(c->ws, plan.lv[0].rt);
+    hip(mg::launch_rho_tilde(rho, f0.mask, f0.q, f0.rt, s), "rho_tilde");
   }
   for (int l = 1; l < c->L; ++l) {
     const Level& a = c->lv[l - 1];

@@ -19,6 +19,13 @@
 //
 // Traffic per sweep: p, f and the three face arrays read once and p written once
 // (6 scalars per cell), plus halo and chunk-boundary overlap served mostly by L2.
+//
+// Density form (finest grid of a hierarchy built from rho, FP64): instead of the three
+// face arrays the sweep reads rt = rho on active cells, +inf elsewhere, and forms each
+// face coefficient as 2 / (rt_L + rt_R), which is 0 wherever a face touches an inactive
+// cell or a wall and otherwise bit for bit the stored coefficient.  That is 4 scalars
+// per cell per sweep instead of 6; the extra divisions are cheap next to the memory
+// time.
 #include "mg_kernels.h"
 
 #include <type_traits>
@@ -26,8 +33,6 @@
 namespace mg {
 
 namespace {
-
-__device__ __forceinline__ int cell(int i, int j, int k, int q) { return (((k << q) + j) << q) + i; }
 
 template <typename T>
 struct Vec2;
@@ -40,6 +45,55 @@ struct Vec2<float> {
   using type = float2;
 };
 
+// Addressing.  A workgroup marches up z, so each load of a step reads one plane of an
+// array.  The plane is a buffer resource (a descriptor in scalar registers, the same for
+// the whole workgroup) and each thread keeps 32-bit byte offsets in the plane, computed
+// once (N <= 1024: a plane is at most 8 MiB).  A plane outside the grid gets a record
+// count of 0, so every load from it returns 0 without a branch.
+using Rsrc = __amdgpu_buffer_rsrc_t;
+constexpr int kBufferWord3 = 0x00020000;   // raw 32-bit-dword buffer, range-checked (gfx9)
+
+template <typename T>
+__device__ __forceinline__ Rsrc plane_rsrc(const T* a, int kk, int q) {
+  const int k = __builtin_amdgcn_readfirstlane(kk);   // uniform: keeps the descriptor scalar
+  const bool in = k >= 0 && k < (1 << q);
+  const T* base = a + (static_cast<long long>(in ? k : 0) << (2 * q));
+  const int bytes = in ? static_cast<int>(sizeof(T)) << (2 * q) : 0;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base), static_cast<short>(0), bytes, kBufferWord3);
+}
+template <typename T>
+__device__ __forceinline__ unsigned off_of(int i, int j, int q) {
+  const int m = (1 << q) - 1;
+  return static_cast<unsigned>(((j & m) << q) | (i & m)) * static_cast<unsigned>(sizeof(T));
+}
+__device__ __forceinline__ double ld1(Rsrc r, unsigned off, double) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ float ld1(Rsrc r, unsigned off, float) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ double2 ld2(Rsrc r, unsigned off, double) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+  double2 d;
+  __builtin_memcpy(&d, &v, sizeof d);
+  return d;
+}
+__device__ __forceinline__ float2 ld2(Rsrc r, unsigned off, float) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+  float2 d;
+  __builtin_memcpy(&d, &v, sizeof d);
+  return d;
+}
+
+// in-plane byte offsets around a thread's x-pair (i even, i+1) in row j
+struct PairOffsets {
+  unsigned c;    // the pair
+  unsigned xl;   // cell i-1
+  unsigned xr;   // cell i+2
+  unsigned yd;   // the pair in row j-1
+  unsigned yu;   // the pair in row j+1
+};
+
 // f and the six face coefficients of one cell: everything but p that its update reads
 template <typename T>
 struct Coef {
@@ -50,20 +104,17 @@ template <typename T>
 __device__ __forceinline__ Coef<T> load_cell(const T* __restrict__ f, const T* __restrict__ bx,
                                              const T* __restrict__ by, const T* __restrict__ bz, int i, int j, int kk,
                                              int q) {
+  // planes outside the grid read as 0 (no coefficients, no source)
   Coef<T> C;
-  const int n = 1 << q, m = n - 1;
-  if (kk < 0 || kk >= n) {
-    C.f = C.xm = C.xp = C.ym = C.yp = C.zm = C.zp = T(0);
-    return C;
-  }
-  const int c = cell(i, j, kk, q);
-  C.f = f[c];
-  C.xm = bx[c];
-  C.xp = bx[cell((i + 1) & m, j, kk, q)];
-  C.ym = by[c];
-  C.yp = by[cell(i, (j + 1) & m, kk, q)];
-  C.zm = bz[c];
-  C.zp = kk < m ? bz[c + (1 << (2 * q))] : T(0);
+  const unsigned oc = off_of<T>(i, j, q), ox = off_of<T>(i + 1, j, q), oy = off_of<T>(i, j + 1, q);
+  const Rsrc xk = plane_rsrc(bx, kk, q), yk = plane_rsrc(by, kk, q);
+  C.f = ld1(plane_rsrc(f, kk, q), oc, T());
+  C.xm = ld1(xk, oc, T());
+  C.xp = ld1(xk, ox, T());
+  C.ym = ld1(yk, oc, T());
+  C.yp = ld1(yk, oy, T());
+  C.zm = ld1(plane_rsrc(bz, kk, q), oc, T());
+  C.zp = ld1(plane_rsrc(bz, kk + 1, q), oc, T());   // top wall: plane n reads 0
   return C;
 }
 
@@ -77,23 +128,16 @@ struct PairRaw {
 
 template <typename T>
 __device__ __forceinline__ void load_pair(PairRaw<T>& R, const T* __restrict__ f, const T* __restrict__ bx,
-                                          const T* __restrict__ by, const T* __restrict__ bz, int i, int j, int kk,
-                                          int q) {
-  using V2 = typename Vec2<T>::type;
-  const int n = 1 << q, m = n - 1;
-  if (kk < 0 || kk >= n) {
-    R.f = R.bx = R.by = R.byu = R.bz = R.bzu = V2{T(0), T(0)};
-    R.bxr = T(0);
-    return;
-  }
-  const int c = cell(i, j, kk, q);
-  R.f = *reinterpret_cast<const V2*>(f + c);
-  R.bx = *reinterpret_cast<const V2*>(bx + c);
-  R.bxr = bx[cell((i + 2) & m, j, kk, q)];
-  R.by = *reinterpret_cast<const V2*>(by + c);
-  R.byu = *reinterpret_cast<const V2*>(by + cell(i, (j + 1) & m, kk, q));
-  R.bz = *reinterpret_cast<const V2*>(bz + c);
-  R.bzu = kk < m ? *reinterpret_cast<const V2*>(bz + c + (1 << (2 * q))) : V2{T(0), T(0)};
+                                          const T* __restrict__ by, const T* __restrict__ bz, const PairOffsets& o,
+                                          int kk, int q) {
+  const Rsrc xk = plane_rsrc(bx, kk, q), yk = plane_rsrc(by, kk, q);
+  R.f = ld2(plane_rsrc(f, kk, q), o.c, T());
+  R.bx = ld2(xk, o.c, T());
+  R.bxr = ld1(xk, o.xr, T());
+  R.by = ld2(yk, o.c, T());
+  R.byu = ld2(yk, o.yu, T());
+  R.bz = ld2(plane_rsrc(bz, kk, q), o.c, T());
+  R.bzu = ld2(plane_rsrc(bz, kk + 1, q), o.c, T());   // top wall: plane n reads 0
 }
 
 // coefficients of the even (ODD = false) or odd (ODD = true) cell of a pair
@@ -120,6 +164,102 @@ __device__ __forceinline__ Coef<T> cell_of(const PairRaw<T>& R) {
   return C;
 }
 
+// ---- density form
+template <typename T>
+__device__ __forceinline__ T beta_rho(T a, T b) { return T(2) / (a + b); }
+
+// f and the in-plane densities around an x-pair of one plane; the pair's own densities
+// (c) come from the z window the kernel keeps
+template <typename T>
+struct PairRho {
+  typename Vec2<T>::type f, c, s, n;   // f, rt of the pair, rt of the pair in rows j-1 and j+1
+  T l, r;                              // rt at i-1 and i+2
+};
+
+// Loads outside the grid are clamped onto plane 0 and their values replaced after the
+// load (no branch around a load, so the compiler keeps everything in registers).
+template <typename T>
+__device__ __forceinline__ typename Vec2<T>::type load_centre(const T* __restrict__ rt, unsigned oc, int kk, int q) {
+  using V2 = typename Vec2<T>::type;
+  const T inf = __builtin_huge_val();
+  const bool in = kk >= 0 && kk < (1 << q);   // beyond a z wall: +inf
+  const V2 v = ld2(plane_rsrc(rt, kk, q), oc, T());
+  return V2{in ? v.x : inf, in ? v.y : inf};
+}
+
+template <typename T>
+__device__ __forceinline__ void load_pair_rho(PairRho<T>& R, const T* __restrict__ f, const T* __restrict__ rt,
+                                              typename Vec2<T>::type centre, const PairOffsets& o, int kk, int q) {
+  using V2 = typename Vec2<T>::type;
+  const int n = 1 << q;
+  const T inf = __builtin_huge_val();
+  const bool in = kk >= 0 && kk < n;
+  const Rsrc rk = plane_rsrc(rt, kk, q);
+  const V2 fv = ld2(plane_rsrc(f, kk, q), o.c, T());   // 0 outside the grid
+  const T l = ld1(rk, o.xl, T());
+  const T r = ld1(rk, o.xr, T());
+  const V2 sv = ld2(rk, o.yd, T());
+  const V2 nv = ld2(rk, o.yu, T());
+  R.c = centre;
+  R.f = fv;
+  R.l = in ? l : inf;
+  R.r = in ? r : inf;
+  R.s = V2{in ? sv.x : inf, in ? sv.y : inf};
+  R.n = V2{in ? nv.x : inf, in ? nv.y : inf};
+}
+
+// coefficients of the even or odd cell of a pair from its densities and the pair's
+// densities on the planes below and above
+template <bool ODD, typename T>
+__device__ __forceinline__ Coef<T> cell_of_rho(const PairRho<T>& R, typename Vec2<T>::type below,
+                                               typename Vec2<T>::type above) {
+  Coef<T> C;
+  if (ODD) {
+    C.f = R.f.y;
+    C.xm = beta_rho(R.c.x, R.c.y);
+    C.xp = beta_rho(R.c.y, R.r);
+    C.ym = beta_rho(R.s.y, R.c.y);
+    C.yp = beta_rho(R.c.y, R.n.y);
+    C.zm = beta_rho(below.y, R.c.y);
+    C.zp = beta_rho(R.c.y, above.y);
+  } else {
+    C.f = R.f.x;
+    C.xm = beta_rho(R.l, R.c.x);
+    C.xp = beta_rho(R.c.x, R.c.y);
+    C.ym = beta_rho(R.s.x, R.c.x);
+    C.yp = beta_rho(R.c.x, R.n.x);
+    C.zm = beta_rho(below.x, R.c.x);
+    C.zp = beta_rho(R.c.x, above.x);
+  }
+  return C;
+}
+
+// one cell's coefficients (the ring cells and the prologue)
+template <typename T>
+__device__ __forceinline__ Coef<T> load_cell_rho(const T* __restrict__ f, const T* __restrict__ rt, int i, int j,
+                                                 int kk, int q) {
+  Coef<T> C;
+  const int n = 1 << q;
+  if (kk < 0 || kk >= n) {
+    C.f = C.xm = C.xp = C.ym = C.yp = C.zm = C.zp = T(0);
+    return C;
+  }
+  const unsigned oc = off_of<T>(i, j, q);
+  const Rsrc rk = plane_rsrc(rt, kk, q);
+  const T rc = ld1(rk, oc, T());
+  C.f = ld1(plane_rsrc(f, kk, q), oc, T());
+  C.xm = beta_rho(ld1(rk, off_of<T>(i - 1, j, q), T()), rc);
+  C.xp = beta_rho(rc, ld1(rk, off_of<T>(i + 1, j, q), T()));
+  C.ym = beta_rho(ld1(rk, off_of<T>(i, j - 1, q), T()), rc);
+  C.yp = beta_rho(rc, ld1(rk, off_of<T>(i, j + 1, q), T()));
+  C.zm = kk > 0 ? beta_rho(ld1(plane_rsrc(rt, kk - 1, q), oc, T()), rc) : T(0);
+  C.zp = kk < n - 1 ? beta_rho(rc, ld1(plane_rsrc(rt, kk + 1, q), oc, T())) : T(0);
+  return C;
+}
+
+__device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
 // A staged plane keeps each row split by column parity, [row][c & 1][c >> 1], so a wave
 // updating one colour reads consecutive words (no LDS bank conflicts).
 template <typename T, int W>
@@ -133,24 +273,25 @@ template <typename T, int W>
 __device__ __forceinline__ void gs(T (*cur)[2][W / 2], int r, int c, T lo, T hi, const Coef<T>& C, T h2, T fs) {
   const T D = C.xm + C.xp + C.ym + C.yp + C.zm + C.zp;
   if (D > T(0)) {
-    const T S = C.xm * at<T, W>(cur, r, c - 1) + C.xp * at<T, W>(cur, r, c + 1) + C.ym * at<T, W>(cur, r - 1, c) +
-                C.yp * at<T, W>(cur, r + 1, c) + C.zm * lo + C.zp * hi;
-    at<T, W>(cur, r, c) = (S - h2 * (C.f - fs)) / D;
+    // explicit fused multiply-adds: the rounding is fixed by the source, whichever form
+    // the coefficients come in
+    const T S = fmad(C.zp, hi, fmad(C.zm, lo, fmad(C.yp, at<T, W>(cur, r + 1, c), fmad(C.ym, at<T, W>(cur, r - 1, c),
+                fmad(C.xp, at<T, W>(cur, r, c + 1), C.xm * at<T, W>(cur, r, c - 1))))));
+    at<T, W>(cur, r, c) = fmad(-h2, C.f - fs, S) / D;
   }
 }
 
-constexpr int kTY = 8;
 
-// Tiles span TX = min(N, 256) cells in x, so for N <= 256 the x halo wraps onto the
-// tile's own cache lines, and TY = 8 rows; one thread per x-pair of tile cells.
-template <typename T, int TX>
-__global__ __launch_bounds__(TX / 2 * kTY) void k_rbgs_fused(const T* __restrict__ pin, T* __restrict__ pout,
+// Tiles of TX x TY cells, one thread per x-pair of tile cells: 64 x 8 and 128 x 8 for
+// N = 64 and 128 (the x halo wraps onto the tile's own cache lines), 128 x 16 above
+// (one wave per tile row; fewer halo rows and ring cells per tile cell than 256 x 8).
+template <typename T, int TX, int TY, bool RHO>
+__global__ __launch_bounds__(TX / 2 * TY) void k_rbgs_fused(const T* __restrict__ pin, T* __restrict__ pout,
                                                               const T* __restrict__ f, const T* __restrict__ bx,
                                                               const T* __restrict__ by, const T* __restrict__ bz,
-                                                              int q, int kc, T h2, int first,
-                                                              const double* __restrict__ fshift) {
+                                                              const T* __restrict__ rt, int q, int kc, T h2,
+                                                              int first, const double* __restrict__ fshift) {
   using V2 = typename Vec2<T>::type;
-  constexpr int TY = kTY;
   constexpr int NT = TX / 2 * TY;
   constexpr int W = TX + 4;                 // columns i0-2 .. i0+TX+1
   constexpr int H = TY + 4;                 // rows    j0-2 .. j0+TY+1
@@ -180,20 +321,22 @@ __global__ __launch_bounds__(TX / 2 * kTY) void k_rbgs_fused(const T* __restrict
   static_assert(TX >= 64, "a wave must not span rows of both parities");
   const int jrow = j0 + jt;
   const int ipair = i0 + 2 * xt;
+  const PairOffsets po{off_of<T>(ipair, jrow, q), off_of<T>(ipair - 1, jrow, q), off_of<T>(ipair + 2, jrow, q),
+                       off_of<T>(ipair, jrow - 1, q), off_of<T>(ipair, jrow + 1, q)};
 
   // ---- staged p planes: global -> registers (one plane ahead) -> LDS
   V2 pn[PER];
-  auto fetch_plane = [&](int kk) {
+  unsigned op[PER];   // in-plane offsets of this thread's pairs of the staged box
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int e = tid + u * NT;
-      if (e < BOX && kk >= 0 && kk < n) {
-        const int r = e / (W / 2), cp = e % (W / 2);
-        pn[u] = *reinterpret_cast<const V2*>(pin + cell((i0 - 2 + 2 * cp) & m, (j0 - 2 + r) & m, kk, q));
-      } else {
-        pn[u] = V2{T(0), T(0)};
-      }
-    }
+  for (int u = 0; u < PER; ++u) {
+    const int e = tid + u * NT;
+    const int r = e / (W / 2), cp = e % (W / 2);
+    op[u] = e < BOX ? off_of<T>(i0 - 2 + 2 * cp, j0 - 2 + r, q) : 0u;   // past the box: a harmless load
+  }
+  auto fetch_plane = [&](int kk) {   // a plane outside the grid reads as 0
+    const Rsrc pk = plane_rsrc(pin, kk, q);
+#pragma unroll
+    for (int u = 0; u < PER; ++u) pn[u] = ld2(pk, op[u], T());
   };
   auto store_plane = [&](int slot) {
 #pragma unroll
@@ -230,29 +373,45 @@ __global__ __launch_bounds__(TX / 2 * kTY) void k_rbgs_fused(const T* __restrict
 
   // first-colour / second-colour cell of this thread's pair on plane kk
   auto first_odd = [&](int kk) { return ((first + jrow + kk) & 1) != 0; };
-  const int rt = jt + 2, ct = 2 * xt + 2;   // the pair's place in a staged plane
+  const int rt_ = jt + 2, ct = 2 * xt + 2;   // the pair's place in a staged plane
 
   // ---- prologue.  Plane kk is staged in slot kk & 3; plane k0-2 of the pair in registers.
   auto slot = [](int kk) { return kk & 3; };
+  // one cell's coefficients in either form
+  auto coef_at = [&](int i, int j, int kk) {
+    if constexpr (RHO)
+      return load_cell_rho(f, rt, i, j, kk, q);
+    else
+      return load_cell(f, bx, by, bz, i, j, kk, q);
+  };
   int rr_, rc_, ri_, rj_;
   PairRaw<T> raw;        // both cells' coefficients of the plane above the current one
+  PairRho<T> rraw;       // density form: the same plane's f and in-plane densities
+  V2 rc_lo, rc_hi;       // density form: the pair's densities on the current plane and two up
   Coef<T> black_cur;     // second colour's coefficients on the current plane
   T below0, below1;      // the pair's finished values on the plane under the current one
   {
-    const Coef<T> red_m1 = load_cell(f, bx, by, bz, ipair + first_odd(k0 - 1), jrow, k0 - 1, q);
-    const Coef<T> red_0 = load_cell(f, bx, by, bz, ipair + first_odd(k0), jrow, k0, q);
-    black_cur = load_cell(f, bx, by, bz, ipair + !first_odd(k0), jrow, k0, q);
+    const Coef<T> red_m1 = coef_at(ipair + first_odd(k0 - 1), jrow, k0 - 1);
+    const Coef<T> red_0 = coef_at(ipair + first_odd(k0), jrow, k0);
+    black_cur = coef_at(ipair + !first_odd(k0), jrow, k0);
     Coef<T> ring_0;
     if (has_ring) {
       ring_cell(k0, rr_, rc_, ri_, rj_);
-      ring_0 = load_cell(f, bx, by, bz, ri_, rj_, k0, q);
+      ring_0 = coef_at(ri_, rj_, k0);
     }
     T pm2_0 = T(0), pm2_1 = T(0);   // the pair on plane k0-2
-    if (k0 - 2 >= 0) {
-      pm2_0 = pin[cell(ipair, jrow, k0 - 2, q)];
-      pm2_1 = pin[cell(ipair + 1, jrow, k0 - 2, q)];
+    {
+      const V2 v = ld2(plane_rsrc(pin, k0 - 2, q), po.c, T());   // 0 below the grid
+      pm2_0 = v.x;
+      pm2_1 = v.y;
     }
-    load_pair(raw, f, bx, by, bz, ipair, jrow, k0 + 1, q);
+    if constexpr (RHO) {
+      rc_lo = load_centre(rt, po.c, k0, q);
+      load_pair_rho(rraw, f, rt, load_centre(rt, po.c, k0 + 1, q), po, k0 + 1, q);
+      rc_hi = load_centre(rt, po.c, k0 + 2, q);
+    } else {
+      load_pair(raw, f, bx, by, bz, po, k0 + 1, q);
+    }
     fetch_plane(k0 - 1);
     store_plane(slot(k0 - 1));
     fetch_plane(k0);
@@ -264,13 +423,13 @@ __global__ __launch_bounds__(TX / 2 * kTY) void k_rbgs_fused(const T* __restrict
     const int sm = slot(k0 - 1), s0 = slot(k0), s1 = slot(k0 + 1);
     if (k0 - 1 >= 0) {
       const int o = first_odd(k0 - 1);
-      gs<T, W>(L[sm], rt, ct + o, o ? pm2_1 : pm2_0, at<T, W>(L[s0], rt, ct + o), red_m1, h2, fs);
+      gs<T, W>(L[sm], rt_, ct + o, o ? pm2_1 : pm2_0, at<T, W>(L[s0], rt_, ct + o), red_m1, h2, fs);
     }
-    below0 = at<T, W>(L[sm], rt, ct);   // own cells: only this thread wrote them
-    below1 = at<T, W>(L[sm], rt, ct + 1);
+    below0 = at<T, W>(L[sm], rt_, ct);   // own cells: only this thread wrote them
+    below1 = at<T, W>(L[sm], rt_, ct + 1);
     {
       const int c = ct + first_odd(k0);
-      gs<T, W>(L[s0], rt, c, at<T, W>(L[sm], rt, c), at<T, W>(L[s1], rt, c), red_0, h2, fs);
+      gs<T, W>(L[s0], rt_, c, at<T, W>(L[sm], rt_, c), at<T, W>(L[s1], rt_, c), red_0, h2, fs);
     }
     if (has_ring) {
       ring_cell(k0, rr_, rc_, ri_, rj_);
@@ -289,32 +448,54 @@ __global__ __launch_bounds__(TX / 2 * kTY) void k_rbgs_fused(const T* __restrict
   auto step = [&](int k, auto odd_tag) {
     constexpr bool ODD1 = decltype(odd_tag)::value;
     const int s0 = slot(k), s1 = slot(k + 1), s2 = slot(k + 2);
-    store_plane(s2);                   // plane k+2
-    fetch_plane(k + 3);
-    PairRaw<T> raw_next;
-    load_pair(raw_next, f, bx, by, bz, ipair, jrow, k + 2, q);
+    // the ring cell's coefficients first: they are used right after the barrier, and
+    // waiting for them must not wait for the prefetches of the planes above
     Coef<T> ring_c;
     if (has_ring) {
       ring_cell(k + 1, rr_, rc_, ri_, rj_);
-      ring_c = load_cell(f, bx, by, bz, ri_, rj_, k + 1, q);
+      ring_c = coef_at(ri_, rj_, k + 1);
+    }
+    store_plane(s2);                   // plane k+2
+    fetch_plane(k + 3);
+    PairRaw<T> raw_next;
+    PairRho<T> rraw_next;
+    V2 rc_next;
+    if constexpr (RHO) {
+      load_pair_rho(rraw_next, f, rt, rc_hi, po, k + 2, q);
+      rc_next = load_centre(rt, po.c, k + 3, q);
+    } else {
+      load_pair(raw_next, f, bx, by, bz, po, k + 2, q);
     }
     __syncthreads();
     if (k + 1 < n) {                   // first colour on plane k+1, tile and ring
       const int c = ct + ODD1;
-      gs<T, W>(L[s1], rt, c, at<T, W>(L[s0], rt, c), at<T, W>(L[s2], rt, c), cell_of<ODD1>(raw), h2, fs);
+      Coef<T> red;
+      if constexpr (RHO)
+        red = cell_of_rho<ODD1>(rraw, rc_lo, rc_hi);
+      else
+        red = cell_of<ODD1>(raw);
+      gs<T, W>(L[s1], rt_, c, at<T, W>(L[s0], rt_, c), at<T, W>(L[s2], rt_, c), red, h2, fs);
       if (has_ring) gs<T, W>(L[s1], rr_, rc_, at<T, W>(L[s0], rr_, rc_), at<T, W>(L[s2], rr_, rc_), ring_c, h2, fs);
     }
     // no barrier: the second colour on plane k reads the first colour on plane k+1 only
     // in its own column, which this thread has just updated
     {                                  // second colour on plane k (same column), plane out
       const int c = ct + ODD1;
-      gs<T, W>(L[s0], rt, c, ODD1 ? below1 : below0, at<T, W>(L[s1], rt, c), black_cur, h2, fs);
-      below0 = at<T, W>(L[s0], rt, ct);
-      below1 = at<T, W>(L[s0], rt, ct + 1);
-      *reinterpret_cast<V2*>(pout + cell(ipair, jrow, k, q)) = V2{below0, below1};
+      gs<T, W>(L[s0], rt_, c, ODD1 ? below1 : below0, at<T, W>(L[s1], rt_, c), black_cur, h2, fs);
+      below0 = at<T, W>(L[s0], rt_, ct);
+      below1 = at<T, W>(L[s0], rt_, ct + 1);
+      *reinterpret_cast<V2*>(reinterpret_cast<char*>(pout + (static_cast<long long>(k) << (2 * q))) + po.c) =
+          V2{below0, below1};
     }
-    black_cur = cell_of<!ODD1>(raw);
-    raw = raw_next;
+    if constexpr (RHO) {
+      black_cur = cell_of_rho<!ODD1>(rraw, rc_lo, rc_hi);
+      rc_lo = rraw.c;
+      rraw = rraw_next;
+      rc_hi = rc_next;
+    } else {
+      black_cur = cell_of<!ODD1>(raw);
+      raw = raw_next;
+    }
   };
   for (int k = k0; k < k1; ++k) {
     if (first_odd(k + 1))
@@ -324,12 +505,12 @@ __global__ __launch_bounds__(TX / 2 * kTY) void k_rbgs_fused(const T* __restrict
   }
 }
 
-template <typename T, int TX>
-hipError_t launch_tx(const T* pin, T* pout, const T* f, const T* bx, const T* by, const T* bz, int q, double h,
-                     int order, const double* fshift, hipStream_t s) {
+template <typename T, int TX, int TY>
+hipError_t launch_tx(const T* pin, T* pout, const T* f, const T* bx, const T* by, const T* bz, const T* rt, int q,
+                     double h, int order, const double* fshift, hipStream_t s) {
   const int n = 1 << q;
-  constexpr int threads = TX / 2 * kTY;
-  const long long tiles = static_cast<long long>(n / TX) * (n / kTY);
+  constexpr int threads = TX / 2 * TY;
+  const long long tiles = static_cast<long long>(n / TX) * (n / TY);
   // z-chunk: as long as possible (overlap planes per chunk) while still giving each
   // compute unit the workgroups it can hold at once (FP64 needs about twice the
   // registers of FP32, so half as many fit)
@@ -340,8 +521,16 @@ hipError_t launch_tx(const T* pin, T* pout, const T* f, const T* bx, const T* by
   const long long blocks = tiles * (n / kc);
   const T h2 = static_cast<T>(h * h);
   const int first = order == 0 ? 0 : 1;   // pre-smoothing: red first; post-smoothing: black first
-  hipLaunchKernelGGL((k_rbgs_fused<T, TX>), dim3(static_cast<unsigned>(blocks)), dim3(threads), 0, s, pin, pout, f,
-                     bx, by, bz, q, kc, h2, first, fshift);
+  const dim3 grid(static_cast<unsigned>(blocks));
+  if constexpr (std::is_same<T, double>::value) {
+    if (rt) {
+      hipLaunchKernelGGL((k_rbgs_fused<T, TX, TY, true>), grid, dim3(threads), 0, s, pin, pout, f, bx, by, bz, rt, q, kc,
+                         h2, first, fshift);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((k_rbgs_fused<T, TX, TY, false>), grid, dim3(threads), 0, s, pin, pout, f, bx, by, bz, rt, q, kc, h2,
+                     first, fshift);
   return hipGetLastError();
 }
 
@@ -350,18 +539,20 @@ hipError_t launch_tx(const T* pin, T* pout, const T* f, const T* bx, const T* by
 int fused_sweep_supported(int q) { return (1 << q) >= 64; }
 
 template <typename T>
-hipError_t launch_rbgs_fused(const T* pin, T* pout, const T* f, const T* bx, const T* by, const T* bz, int q,
-                             double h, int order, const double* fshift, hipStream_t s) {
+hipError_t launch_rbgs_fused(const T* pin, T* pout, const T* f, const T* bx, const T* by, const T* bz, const T* rt,
+                             int q, double h, int order, const double* fshift, hipStream_t s) {
   const int n = 1 << q;
   if (n < 64) return hipErrorInvalidValue;
-  if (n == 64) return launch_tx<T, 64>(pin, pout, f, bx, by, bz, q, h, order, fshift, s);
-  if (n == 128) return launch_tx<T, 128>(pin, pout, f, bx, by, bz, q, h, order, fshift, s);
-  return launch_tx<T, 256>(pin, pout, f, bx, by, bz, q, h, order, fshift, s);
+  if (!std::is_same<T, double>::value && rt) return hipErrorInvalidValue;   // density form is FP64 only
+  if (n == 64) return launch_tx<T, 64, 8>(pin, pout, f, bx, by, bz, rt, q, h, order, fshift, s);
+  if (n == 128) return launch_tx<T, 128, 8>(pin, pout, f, bx, by, bz, rt, q, h, order, fshift, s);
+  return launch_tx<T, 128, 16>(pin, pout, f, bx, by, bz, rt, q, h, order, fshift, s);
 }
 
 template hipError_t launch_rbgs_fused<double>(const double*, double*, const double*, const double*, const double*,
-                                              const double*, int, double, int, const double*, hipStream_t);
+                                              const double*, const double*, int, double, int, const double*,
+                                              hipStream_t);
 template hipError_t launch_rbgs_fused<float>(const float*, float*, const float*, const float*, const float*,
-                                             const float*, int, double, int, const double*, hipStream_t);
+                                             const float*, const float*, int, double, int, const double*, hipStream_t);
 
 }  // namespace mg

@@ -14,6 +14,10 @@ namespace mg {
 // beta_f = o_f 2/(rho_L + rho_R); with rho == nullptr the open-face areas o_f (0 or 1)
 hipError_t launch_coeffs_from_rho(const double* rho, const uint8_t* mask, int q,
                                   double* bx, double* by, double* bz, hipStream_t s);
+// rt = rho on active cells (mask after setup), +inf elsewhere: the density form of the
+// finest coefficients, beta_f = 2/(rt_L + rt_R), which the finest-grid passes may read
+// instead of the three face arrays (bit-identical coefficients)
+hipError_t launch_rho_tilde(const double* rho, const uint8_t* mask, int q, double* rt, hipStream_t s);
 // coarse rho = mean of rho over the active children (1 if none)
 hipError_t launch_restrict_rho(const double* rho, const uint8_t* mask, int qc, double* crho, hipStream_t s);
 // beta = area * 2/(rho_L + rho_R) in place on the open faces
@@ -34,12 +38,13 @@ hipError_t launch_rbgs_half(T* p, const T* f, const T* bx, const T* by, const T*
                             double h, int colour, const double* fshift, hipStream_t s);
 // One full red-black sweep in one pass, out of place (pin -> pout, distinct buffers);
 // order 0 = red then black, 1 = black then red.  Grids with at least 64 cells per side.
+// rt != nullptr (FP64 only): coefficients from the density form instead of bx, by, bz.
 int fused_sweep_supported(int q);
 template <typename T>
-hipError_t launch_rbgs_fused(const T* pin, T* pout, const T* f, const T* bx, const T* by, const T* bz, int q,
-                             double h, int order, const double* fshift, hipStream_t s);
+hipError_t launch_rbgs_fused(const T* pin, T* pout, const T* f, const T* bx, const T* by, const T* bz, const T* rt,
+                             int q, double h, int order, const double* fshift, hipStream_t s);
 template <typename T>
-hipError_t launch_residual_restrict(const T* p, const T* f, const T* bx, const T* by, const T* bz,
+hipError_t launch_residual_restrict(const T* p, const T* f, const T* bx, const T* by, const T* bz, const T* rt,
                                     int q, double h, const double* fshift, T* fc, T* ec_zero,
                                     hipStream_t s);
 template <typename T>
@@ -74,13 +79,14 @@ hipError_t launch_coarse_cycle(const CoarseCycle<T>& a, hipStream_t s);
 // r32 = float(r) and e32 = 0 (mixed-precision refinement); returns the block count used.
 // optional outputs: r32 = float(r) with e32 = 0; r64 = r with z64 = 0 (flexible CG)
 hipError_t launch_residual_norm(const double* p, const double* f, const double* bx, const double* by,
-                                const double* bz, int q, double h, const double* fshift,
+                                const double* bz, const double* rt, int q, double h, const double* fshift,
                                 float* r32, float* e32_zero, double* r64, double* z64, double* partials,
                                 int* nblocks, hipStream_t s);
 // flexible CG: w = A d with partial d.w and d.r; the update p += alpha d, r -= alpha w
 // (alpha = dr/dw read on the device) with partial ||r||^2; partial z.w; d = z + beta d
-hipError_t launch_fcg_aw(const double* d, const double* r, const double* bx, const double* by, const double* bz, int q,
-                         double h, double* w, double* part_dw, double* part_dr, int* nblocks, hipStream_t s);
+hipError_t launch_fcg_aw(const double* d, const double* r, const double* bx, const double* by, const double* bz,
+                         const double* rt, int q, double h, double* w, double* part_dw, double* part_dr, int* nblocks,
+                         hipStream_t s);
 hipError_t launch_fcg_update(double* p, double* r, const double* d, const double* w, const double* s_dr,
                              const double* s_dw, int q, double* z_zero, float* r32, float* e32_zero, double* part_rr,
                              int* nblocks, hipStream_t s);

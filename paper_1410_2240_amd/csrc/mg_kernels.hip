@@ -75,19 +75,89 @@ struct V2of<float> {
   using type = float2;
 };
 
+__device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
 template <typename T>
 __device__ __forceinline__ typename V2of<T>::type ld2(const T* __restrict__ a, int c) {
   return *reinterpret_cast<const typename V2of<T>::type*>(a + c);
 }
 
+// Face coefficients around the x-neighbour pair (i, j, k), (i+1, j, k) with i even:
+// the x faces at i, i+1, i+2 (low-face indexing, so x1 is the face between the two
+// cells) and the low / high y and z faces of both cells.
+template <typename T>
+struct PairFaces {
+  using V2 = typename V2of<T>::type;
+  T x0, x1, x2;
+  V2 ym, yp, zm, zp;
+};
+
+template <typename T>
+__device__ __forceinline__ PairFaces<T> pair_faces(const T* __restrict__ bx, const T* __restrict__ by,
+                                                   const T* __restrict__ bz, int i, int j, int k, int q) {
+  using V2 = typename V2of<T>::type;
+  const int m = (1 << q) - 1, nn = 1 << (2 * q);
+  const int c = cell(i, j, k, q);
+  PairFaces<T> F;
+  const V2 bxv = ld2(bx, c);
+  F.x0 = bxv.x;
+  F.x1 = bxv.y;
+  F.x2 = bx[cell((i + 2) & m, j, k, q)];
+  F.ym = ld2(by, c);
+  F.yp = ld2(by, cell(i, (j + 1) & m, k, q));
+  F.zm = ld2(bz, c);   // 0 on the bottom wall
+  F.zp = k < m ? ld2(bz, c + nn) : V2{T(0), T(0)};
+  return F;
+}
+
+// The density form of the same coefficients, for the finest grid of a hierarchy built
+// from the cell density: rt holds rho on active cells and +inf on every other cell,
+// and a neighbour beyond a z wall counts as +inf too.  beta = 2 / (rt_L + rt_R) is then
+// 0 on every face that touches an inactive cell or a wall, and on open faces it is bit
+// for bit the stored coefficient (the sum is commutative and the division correctly
+// rounded).  A sweep then reads one density instead of three face arrays.
+template <typename T>
+__device__ __forceinline__ T beta_rho(T a, T b) { return T(2) / (a + b); }
+
+template <typename T>
+__device__ __forceinline__ PairFaces<T> pair_faces_rho(const T* __restrict__ rt, int i, int j, int k, int q) {
+  using V2 = typename V2of<T>::type;
+  const int m = (1 << q) - 1, nn = 1 << (2 * q);
+  const int c = cell(i, j, k, q);
+  const T inf = __builtin_huge_val();
+  const V2 rc = ld2(rt, c);
+  const T rl = rt[cell((i - 1) & m, j, k, q)], rr = rt[cell((i + 2) & m, j, k, q)];
+  const V2 rs = ld2(rt, cell(i, (j - 1) & m, k, q)), rn = ld2(rt, cell(i, (j + 1) & m, k, q));
+  const V2 rd = k > 0 ? ld2(rt, c - nn) : V2{inf, inf};
+  const V2 ru = k < m ? ld2(rt, c + nn) : V2{inf, inf};
+  PairFaces<T> F;
+  F.x0 = beta_rho(rl, rc.x);
+  F.x1 = beta_rho(rc.x, rc.y);
+  F.x2 = beta_rho(rc.y, rr);
+  F.ym = V2{beta_rho(rs.x, rc.x), beta_rho(rs.y, rc.y)};
+  F.yp = V2{beta_rho(rc.x, rn.x), beta_rho(rc.y, rn.y)};
+  F.zm = V2{beta_rho(rd.x, rc.x), beta_rho(rd.y, rc.y)};
+  F.zp = V2{beta_rho(rc.x, ru.x), beta_rho(rc.y, ru.y)};
+  return F;
+}
+
+// Where the face coefficients of a grid come from: the stored arrays bx, by, bz, or
+// (finest grid of a hierarchy built from rho, FP64) the density form rt.
+template <typename T>
+struct Coefs {
+  const T* bx;
+  const T* by;
+  const T* bz;
+  const T* rt;
+};
+
 // Residuals r = (f - fs) - h^-2 sum_f beta_f (p_nb - p_c) of the x-neighbour pair
 // (i, j, k), (i+1, j, k) with i even, 0 on inactive cells.  All loads but the two
 // outer x neighbours are 2-wide and contiguous across adjacent threads.
-template <typename T>
-__device__ __forceinline__ void pair_residual(const T* __restrict__ p, const T* __restrict__ f,
-                                              const T* __restrict__ bx, const T* __restrict__ by,
-                                              const T* __restrict__ bz, int i, int j, int k, int q, T inv_h2, T fs,
-                                              T& r0, T& r1) {
+template <typename T, bool RHO>
+__device__ __forceinline__ void pair_residual(const T* __restrict__ p, const T* __restrict__ f, const Coefs<T>& K,
+                                              int i, int j, int k, int q, T inv_h2, T fs, T& r0, T& r1) {
   using V2 = typename V2of<T>::type;
   const int m = (1 << q) - 1, nn = 1 << (2 * q);
   const int c = cell(i, j, k, q);
@@ -97,19 +167,21 @@ __device__ __forceinline__ void pair_residual(const T* __restrict__ p, const T* 
   const V2 pzd = k > 0 ? ld2(p, c - nn) : pc;
   const V2 pzu = k < m ? ld2(p, c + nn) : pc;
   const V2 fv = f ? ld2(f, c) : V2{T(0), T(0)};
-  const V2 bxv = ld2(bx, c);
-  const T bxr = bx[cell((i + 2) & m, j, k, q)];
-  const V2 byv = ld2(by, c), byu = ld2(by, cell(i, (j + 1) & m, k, q));
-  const V2 bzv = ld2(bz, c);
-  const V2 bzu = k < m ? ld2(bz, c + nn) : V2{T(0), T(0)};
-  const T D0 = bxv.x + bxv.y + byv.x + byu.x + bzv.x + bzu.x;
-  const T D1 = bxv.y + bxr + byv.y + byu.y + bzv.y + bzu.y;
-  const T s0 = bxv.x * (pl - pc.x) + bxv.y * (pc.y - pc.x) + byv.x * (pyd.x - pc.x) + byu.x * (pyu.x - pc.x) +
-               bzv.x * (pzd.x - pc.x) + bzu.x * (pzu.x - pc.x);
-  const T s1 = bxv.y * (pc.x - pc.y) + bxr * (pr - pc.y) + byv.y * (pyd.y - pc.y) + byu.y * (pyu.y - pc.y) +
-               bzv.y * (pzd.y - pc.y) + bzu.y * (pzu.y - pc.y);
-  r0 = D0 > T(0) ? (fv.x - fs) - inv_h2 * s0 : T(0);
-  r1 = D1 > T(0) ? (fv.y - fs) - inv_h2 * s1 : T(0);
+  PairFaces<T> F;
+  if constexpr (RHO)
+    F = pair_faces_rho(K.rt, i, j, k, q);
+  else
+    F = pair_faces(K.bx, K.by, K.bz, i, j, k, q);
+  const T D0 = F.x0 + F.x1 + F.ym.x + F.yp.x + F.zm.x + F.zp.x;
+  const T D1 = F.x1 + F.x2 + F.ym.y + F.yp.y + F.zm.y + F.zp.y;
+  // explicit fused multiply-adds: the rounding is fixed by the source, so both forms
+  // of the coefficients give the same bits
+  const T s0 = fmad(F.zp.x, pzu.x - pc.x, fmad(F.zm.x, pzd.x - pc.x, fmad(F.yp.x, pyu.x - pc.x,
+               fmad(F.ym.x, pyd.x - pc.x, fmad(F.x1, pc.y - pc.x, F.x0 * (pl - pc.x))))));
+  const T s1 = fmad(F.zp.y, pzu.y - pc.y, fmad(F.zm.y, pzd.y - pc.y, fmad(F.yp.y, pyu.y - pc.y,
+               fmad(F.ym.y, pyd.y - pc.y, fmad(F.x2, pr - pc.y, F.x1 * (pc.x - pc.y))))));
+  r0 = D0 > T(0) ? fmad(-inv_h2, s0, fv.x - fs) : T(0);
+  r1 = D1 > T(0) ? fmad(-inv_h2, s1, fv.y - fs) : T(0);
 }
 
 // ----------------------------------------------------------------------------- setup
@@ -140,6 +212,14 @@ __global__ __launch_bounds__(kBlock) void k_coeffs_from_rho(const double* __rest
 
 // Density moved cell centre to cell centre: mean over the active children, 1 when
 // there is none (such a coarse cell has only closed faces).
+// density form of the finest coefficients: rt = rho on active cells, +inf elsewhere
+__global__ __launch_bounds__(kBlock) void k_rho_tilde(const double* __restrict__ rho, const uint8_t* __restrict__ mask,
+                                                      int total, double* __restrict__ rt) {
+  const int c = blockIdx.x * kBlock + threadIdx.x;
+  if (c >= total) return;
+  rt[c] = mask[c] ? rho[c] : __builtin_huge_val();
+}
+
 __global__ __launch_bounds__(kBlock) void k_restrict_rho(const double* __restrict__ rho, const uint8_t* __restrict__ mask,
                                                          int qc, double* __restrict__ crho) {
   const int mc = (1 << qc) - 1, q = qc + 1;
@@ -304,34 +384,31 @@ __global__ __launch_bounds__(kBlock) void k_rbgs_half(T* __restrict__ p, const T
 
 // fc = mean over the 8 children of r = (f - fshift) - A p; ec = 0.  One thread per
 // coarse cell: its children are two x-pairs on each of two rows and two planes.
-template <typename T>
-__device__ __forceinline__ void restrict_cell(const T* __restrict__ p, const T* __restrict__ f,
-                                              const T* __restrict__ bx, const T* __restrict__ by,
-                                              const T* __restrict__ bz, int q, T inv_h2, T fs, T* __restrict__ fc,
-                                              T* __restrict__ ec, int C) {
+template <typename T, bool RHO>
+__device__ __forceinline__ void restrict_cell(const T* __restrict__ p, const T* __restrict__ f, const Coefs<T>& K,
+                                              int q, T inv_h2, T fs, T* __restrict__ fc, T* __restrict__ ec, int C) {
   const int qc = q - 1, mc = (1 << qc) - 1;
-  const int I = C & mc, J = (C >> qc) & mc, K = C >> (2 * qc);
+  const int I = C & mc, J = (C >> qc) & mc, Kz = C >> (2 * qc);
   T sum = T(0);
 #pragma unroll
   for (int d = 0; d < 4; ++d) {
     T r0, r1;
-    pair_residual(p, f, bx, by, bz, 2 * I, 2 * J + (d & 1), 2 * K + (d >> 1), q, inv_h2, fs, r0, r1);
+    pair_residual<T, RHO>(p, f, K, 2 * I, 2 * J + (d & 1), 2 * Kz + (d >> 1), q, inv_h2, fs, r0, r1);
     sum += r0 + r1;
   }
   fc[C] = sum * T(0.125);
   ec[C] = T(0);
 }
 
-template <typename T>
+template <typename T, bool RHO>
 __global__ __launch_bounds__(kBlock) void k_residual_restrict(const T* __restrict__ p, const T* __restrict__ f,
-                                                              const T* __restrict__ bx, const T* __restrict__ by,
-                                                              const T* __restrict__ bz, int q, T inv_h2,
+                                                              Coefs<T> K, int q, T inv_h2,
                                                               const double* __restrict__ fshift,
                                                               T* __restrict__ fc, T* __restrict__ ec) {
   const long long t = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
   if (t >= (1LL << (3 * (q - 1)))) return;
   const T fs = fshift ? static_cast<T>(*fshift) : T(0);
-  restrict_cell(p, f, bx, by, bz, q, inv_h2, fs, fc, ec, static_cast<int>(t));
+  restrict_cell<T, RHO>(p, f, K, q, inv_h2, fs, fc, ec, static_cast<int>(t));
 }
 
 // p += mask * trilinear(ec); 1-D weights 3/4 (parent) and 1/4 (nearer neighbour),
@@ -451,7 +528,8 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle(CoarseCycle<T> 
       }
       const T fs = (l == 0 && a.fshift) ? static_cast<T>(*a.fshift) : T(0);
       for (int C = tid; C < (1 << (3 * (a.q[l] - 1))); C += kCoarseThreads)
-        restrict_cell(a.e[l], a.f[l], a.bx[l], a.by[l], a.bz[l], a.q[l], a.inv_h2[l], fs, a.f[l + 1], a.e[l + 1], C);
+        restrict_cell<T, false>(a.e[l], a.f[l], Coefs<T>{a.bx[l], a.by[l], a.bz[l], nullptr}, a.q[l], a.inv_h2[l], fs,
+                                a.f[l + 1], a.e[l + 1], C);
       __syncthreads();
     }
   }
@@ -488,10 +566,9 @@ __device__ __forceinline__ double block_sum(double v) {
   return s;   // valid in thread 0
 }
 
+template <bool RHO>
 __global__ __launch_bounds__(kBlock) void k_residual_norm(const double* __restrict__ p, const double* __restrict__ f,
-                                                          const double* __restrict__ bx,
-                                                          const double* __restrict__ by,
-                                                          const double* __restrict__ bz, int q, double inv_h2,
+                                                          Coefs<double> K, int q, double inv_h2,
                                                           const double* __restrict__ fshift,
                                                           float* __restrict__ r32, float* __restrict__ e32,
                                                           double* __restrict__ r64, double* __restrict__ z64,
@@ -503,8 +580,8 @@ __global__ __launch_bounds__(kBlock) void k_residual_norm(const double* __restri
   for (int t = blockIdx.x * kBlock + threadIdx.x; t < pairs; t += gridDim.x * kBlock) {
     const int i = 2 * (t & (m >> 1)), j = (t >> (q - 1)) & m, k = t >> (2 * q - 1);
     double r0, r1;
-    pair_residual(p, f, bx, by, bz, i, j, k, q, inv_h2, fs, r0, r1);
-    acc += r0 * r0 + r1 * r1;
+    pair_residual<double, RHO>(p, f, K, i, j, k, q, inv_h2, fs, r0, r1);
+    acc = fmad(r1, r1, fmad(r0, r0, acc));
     const int c = cell(i, j, k, q);
     if (r32) {
       *reinterpret_cast<float2*>(r32 + c) = float2{static_cast<float>(r0), static_cast<float>(r1)};
@@ -620,9 +697,9 @@ __global__ __launch_bounds__(kBlock) void k_coeff_grad(const double* __restrict_
 // and end in the fixed-order two-pass block sums.
 
 // w = A d, partial sums of d.w and d.r
+template <bool RHO>
 __global__ __launch_bounds__(kBlock) void k_fcg_aw(const double* __restrict__ d, const double* __restrict__ r,
-                                                   const double* __restrict__ bx, const double* __restrict__ by,
-                                                   const double* __restrict__ bz, int q, double inv_h2,
+                                                   Coefs<double> K, int q, double inv_h2,
                                                    double* __restrict__ w, double* __restrict__ part_dw,
                                                    double* __restrict__ part_dr) {
   const int m = (1 << q) - 1;
@@ -632,13 +709,13 @@ __global__ __launch_bounds__(kBlock) void k_fcg_aw(const double* __restrict__ d,
     const int i = 2 * (t & (m >> 1)), j = (t >> (q - 1)) & m, k = t >> (2 * q - 1);
     double a0, a1;
     // the residual of f = 0 is -A d
-    pair_residual<double>(d, nullptr, bx, by, bz, i, j, k, q, inv_h2, 0.0, a0, a1);
+    pair_residual<double, RHO>(d, nullptr, K, i, j, k, q, inv_h2, 0.0, a0, a1);
     const int c = cell(i, j, k, q);
     const double2 dv = ld2(d, c), rv = ld2(r, c);
     const double2 wv = double2{-a0, -a1};
     *reinterpret_cast<double2*>(w + c) = wv;
-    dw += dv.x * wv.x + dv.y * wv.y;
-    dr += dv.x * rv.x + dv.y * rv.y;
+    dw = fmad(dv.y, wv.y, fmad(dv.x, wv.x, dw));
+    dr = fmad(dv.y, rv.y, fmad(dv.x, rv.x, dr));
   }
   const double s1 = block_sum(dw);
   const double s2 = block_sum(dr);
@@ -796,6 +873,11 @@ hipError_t launch_setup_fine(const double* ubx, const double* uby, const double*
   return hipGetLastError();
 }
 
+hipError_t launch_rho_tilde(const double* rho, const uint8_t* mask, int q, double* rt, hipStream_t s) {
+  hipLaunchKernelGGL(k_rho_tilde, dim3(grid_for(1LL << (3 * q))), dim3(kBlock), 0, s, rho, mask, 1 << (3 * q), rt);
+  return hipGetLastError();
+}
+
 hipError_t launch_restrict_rho(const double* rho, const uint8_t* mask, int qc, double* crho, hipStream_t s) {
   hipLaunchKernelGGL(k_restrict_rho, dim3(grid_for(1LL << (3 * qc))), dim3(kBlock), 0, s, rho, mask, qc, crho);
   return hipGetLastError();
@@ -828,11 +910,15 @@ hipError_t launch_rbgs_half(T* p, const T* f, const T* bx, const T* by, const T*
 }
 
 template <typename T>
-hipError_t launch_residual_restrict(const T* p, const T* f, const T* bx, const T* by, const T* bz, int q, double h,
-                                    const double* fshift, T* fc, T* ec, hipStream_t s) {
+hipError_t launch_residual_restrict(const T* p, const T* f, const T* bx, const T* by, const T* bz, const T* rt, int q,
+                                    double h, const double* fshift, T* fc, T* ec, hipStream_t s) {
   const T inv_h2 = static_cast<T>(1.0 / (h * h));
-  hipLaunchKernelGGL(k_residual_restrict<T>, dim3(grid_for(1LL << (3 * (q - 1)))), dim3(kBlock), 0, s, p, f, bx, by,
-                     bz, q, inv_h2, fshift, fc, ec);
+  const Coefs<T> K{bx, by, bz, rt};
+  const dim3 grid(grid_for(1LL << (3 * (q - 1))));
+  if (rt)
+    hipLaunchKernelGGL((k_residual_restrict<T, true>), grid, dim3(kBlock), 0, s, p, f, K, q, inv_h2, fshift, fc, ec);
+  else
+    hipLaunchKernelGGL((k_residual_restrict<T, false>), grid, dim3(kBlock), 0, s, p, f, K, q, inv_h2, fshift, fc, ec);
   return hipGetLastError();
 }
 
@@ -849,12 +935,17 @@ hipError_t launch_coarse_solve(const T* f, T* e, const double* pinv, const uint8
 }
 
 hipError_t launch_residual_norm(const double* p, const double* f, const double* bx, const double* by,
-                                const double* bz, int q, double h, const double* fshift, float* r32,
+                                const double* bz, const double* rt, int q, double h, const double* fshift, float* r32,
                                 float* e32, double* r64, double* z64, double* partials, int* nblocks,
                                 hipStream_t s) {
   const int nb = reduction_blocks(1LL << (3 * q - 1));
-  hipLaunchKernelGGL(k_residual_norm, dim3(nb), dim3(kBlock), 0, s, p, f, bx, by, bz, q, 1.0 / (h * h), fshift, r32,
-                     e32, r64, z64, partials);
+  const Coefs<double> K{bx, by, bz, rt};
+  if (rt)
+    hipLaunchKernelGGL(k_residual_norm<true>, dim3(nb), dim3(kBlock), 0, s, p, f, K, q, 1.0 / (h * h), fshift, r32,
+                       e32, r64, z64, partials);
+  else
+    hipLaunchKernelGGL(k_residual_norm<false>, dim3(nb), dim3(kBlock), 0, s, p, f, K, q, 1.0 / (h * h), fshift, r32,
+                       e32, r64, z64, partials);
   *nblocks = nb;
   return hipGetLastError();
 }
@@ -897,10 +988,15 @@ hipError_t launch_coeff_grad(const double* mu, const double* p, int batch, const
 }
 
 
-hipError_t launch_fcg_aw(const double* d, const double* r, const double* bx, const double* by, const double* bz, int q,
-                         double h, double* w, double* part_dw, double* part_dr, int* nblocks, hipStream_t s) {
+hipError_t launch_fcg_aw(const double* d, const double* r, const double* bx, const double* by, const double* bz,
+                         const double* rt, int q, double h, double* w, double* part_dw, double* part_dr, int* nblocks,
+                         hipStream_t s) {
   const int nb = reduction_blocks(1LL << (3 * q - 1));
-  hipLaunchKernelGGL(k_fcg_aw, dim3(nb), dim3(kBlock), 0, s, d, r, bx, by, bz, q, 1.0 / (h * h), w, part_dw, part_dr);
+  const Coefs<double> K{bx, by, bz, rt};
+  if (rt)
+    hipLaunchKernelGGL(k_fcg_aw<true>, dim3(nb), dim3(kBlock), 0, s, d, r, K, q, 1.0 / (h * h), w, part_dw, part_dr);
+  else
+    hipLaunchKernelGGL(k_fcg_aw<false>, dim3(nb), dim3(kBlock), 0, s, d, r, K, q, 1.0 / (h * h), w, part_dw, part_dr);
   *nblocks = nb;
   return hipGetLastError();
 }
@@ -956,8 +1052,8 @@ hipError_t launch_project(double* ux, double* uy, double* uz, const double* rx, 
 #define MG_INSTANTIATE(T)                                                                                        \
   template hipError_t launch_rbgs_half<T>(T*, const T*, const T*, const T*, const T*, int, double, int,          \
                                           const double*, hipStream_t);                                           \
-  template hipError_t launch_residual_restrict<T>(const T*, const T*, const T*, const T*, const T*, int, double, \
-                                                  const double*, T*, T*, hipStream_t);                           \
+  template hipError_t launch_residual_restrict<T>(const T*, const T*, const T*, const T*, const T*, const T*, int, \
+                                                  double, const double*, T*, T*, hipStream_t);                   \
   template hipError_t launch_prolong_add<T>(const T*, T*, const uint8_t*, int, hipStream_t);                     \
   template hipError_t launch_coarse_solve<T>(const T*, T*, const double*, const uint8_t*, hipStream_t);    \
   template hipError_t launch_coarse_cycle<T>(const CoarseCycle<T>&, hipStream_t);

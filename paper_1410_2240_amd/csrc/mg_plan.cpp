@@ -55,6 +55,8 @@ int build_plan(int n, int flags, Plan* plan) {
     lv.f = l > 0 ? c.take(cells * 8) : kAbsent;
     lv.e = l > 0 ? c.take(cells * 8) : kAbsent;
     lv.t = c.take(cells * 8);
+    // finest grid: the density form of the face coefficients (hierarchies built from rho)
+    lv.rt = l == 0 ? c.take(cells * 8) : kAbsent;
     if (mixed) {
       lv.bx32 = c.take(cells * 4);
       lv.by32 = c.take(cells * 4);

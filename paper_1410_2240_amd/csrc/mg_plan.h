@@ -30,6 +30,7 @@ struct LevelPlan {
   size_t mask = 0;                 // uint8 activity
   size_t f = 0, e = 0;             // right-hand side / correction (levels >= 1)
   size_t t = 0;                    // second buffer for out-of-place sweeps
+  size_t rt = kAbsent;             // level 0 only: rho on active cells, +inf elsewhere
   // FP32 arrays (mixed precision only)
   size_t bx32 = 0, by32 = 0, bz32 = 0;
   size_t f32 = 0, e32 = 0, t32 = 0;

@@ -1,0 +1,99 @@
+"""The density form of the finest-grid coefficients against the stored face arrays.
+
+A hierarchy set up from the cell density lets the finest-grid passes (the one-pass
+sweep, residual-and-restrict, the residual norm, w = A d of flexible CG) form each
+face coefficient as 2 / (rt_L + rt_R) from rt = rho on active cells, +inf elsewhere,
+instead of reading the three face arrays.  On open faces that is the stored
+coefficient bit for bit (the sum is commutative and the division correctly rounded),
+and on every other face it is 0, so a hierarchy built from rho and one built from
+the equivalent face arrays must give identical bits in every pass and every solve.
+Sizes 64, 128 and 256 cover the three tile widths of the one-pass sweep; the field
+is the steep-crest workload with its immersed body (body faces, dropped cells, walls).
+The oracle comparison pins the density form to the paper's operator directly.
+"""
+import numpy as np
+import pytest
+import torch
+
+import fields
+from oracle import multigrid as omg
+from oracle.operator import face_coeffs_from_rho, project
+from tests.gpu_helpers import dev, host, maxrel
+
+pytestmark = pytest.mark.gpu
+
+
+def pair(N, mixed=False, krylov=False, name="c5"):
+    from paper_1410_2240_amd import MG, coeffs_from_rho
+    inp = fields.make(name, N)
+    rho, mask = dev(inp.rho), dev(inp.mask)
+    a = MG.from_rho(rho, mask, mixed=mixed, krylov=krylov)
+    b = MG(*coeffs_from_rho(rho, mask), mask, mixed=mixed, krylov=krylov)
+    return inp, a, b
+
+
+def fields_for(inp, seed):
+    g = np.random.default_rng(seed)
+    live = inp.mask.astype(bool)
+    p = np.where(live, g.standard_normal(inp.rho.shape), 0.0)
+    f = project(g.standard_normal(inp.rho.shape), live)
+    return dev(p), dev(f)
+
+
+@pytest.fixture(scope="module", params=[64, 128, 256])
+def mgpair(request):
+    return pair(request.param)
+
+
+@pytest.mark.parametrize("order", [0, 1])
+@pytest.mark.parametrize("sweeps", [1, 2])
+def test_sweep_bitwise(mgpair, order, sweeps):
+    inp, a, b = mgpair
+    print(f"density-form sweep N={inp.N} order={order} sweeps={sweeps}", flush=True)
+    p, f = fields_for(inp, 7)
+    pa = a.smooth(0, p.clone(), f, sweeps, order)
+    pb = b.smooth(0, p.clone(), f, sweeps, order)
+    assert torch.equal(pa, pb)
+
+
+def test_residual_restrict_and_vcycle_bitwise(mgpair):
+    inp, a, b = mgpair
+    print(f"density-form residual/vcycle N={inp.N}", flush=True)
+    p, f = fields_for(inp, 8)
+    assert torch.equal(a.residual_restrict(0, p, f), b.residual_restrict(0, p, f))
+    assert torch.equal(a.vcycle(p.clone(), f), b.vcycle(p.clone(), f))
+
+
+def test_solve_bitwise(mgpair):
+    inp, a, b = mgpair
+    print(f"density-form solve N={inp.N}", flush=True)
+    f = dev(inp.f)
+    pa, ha, _ = a.solve(f, tol=1e-10, max_cycles=60, raise_on_fail=False)
+    pb, hb, _ = b.solve(f, tol=1e-10, max_cycles=60, raise_on_fail=False)
+    assert ha == hb
+    assert torch.equal(pa, pb)
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_fcg_and_mixed_bitwise(mixed):
+    inp, a, b = pair(128, mixed=mixed, krylov=True)
+    print(f"density-form FCG mixed={mixed}", flush=True)
+    f = dev(inp.f)
+    pa, ha, _ = a.solve(f, tol=1e-10, max_cycles=40)
+    pb, hb, _ = b.solve(f, tol=1e-10, max_cycles=40)
+    assert ha == hb
+    assert torch.equal(pa, pb)
+
+
+@pytest.mark.parametrize("order", [0, 1])
+def test_sweep_matches_oracle(order):
+    """The density-form sweep against the oracle's two half-sweeps (64^3, crest + body)."""
+    inp, a, _ = pair(64)
+    H = omg.setup(*face_coeffs_from_rho(inp.rho, inp.mask), inp.mask, inp.h)
+    lev = H.levels[0]
+    g = np.random.default_rng(9)
+    p = np.where(lev.mask, g.standard_normal(lev.bx.shape), 0.0)
+    f = project(g.standard_normal(lev.bx.shape), lev.mask)
+    want = omg.smooth(p, f, lev, 2, (omg.RED, omg.BLACK) if order == 0 else (omg.BLACK, omg.RED))
+    got = host(a.smooth(0, dev(p), dev(f), 2, order))
+    assert maxrel(got, want) <= 1e-13
