@@ -22,10 +22,10 @@
 //
 // Density form (finest grid of a hierarchy built from rho, FP64): instead of the three
 // face arrays the sweep reads rt = rho on active cells, +inf elsewhere, and forms each
-// face coefficient as 2 / (rt_L + rt_R), which is 0 wherever a face touches an inactive
-// cell or a wall and otherwise bit for bit the stored coefficient.  That is 4 scalars
-// per cell per sweep instead of 6; the extra divisions are cheap next to the memory
-// time.
+// face coefficient as 2 / (rt_L + rt_R) (face_beta, as the setup does), which is 0
+// wherever a face touches an inactive cell or a wall and otherwise bit for bit the
+// stored coefficient.  That is 4 scalars per cell per sweep instead of 6, for nine
+// reciprocals per x-pair and plane (each face once).
 #include "mg_kernels.h"
 
 #include <type_traits>
@@ -166,7 +166,7 @@ __device__ __forceinline__ Coef<T> cell_of(const PairRaw<T>& R) {
 
 // ---- density form
 template <typename T>
-__device__ __forceinline__ T beta_rho(T a, T b) { return T(2) / (a + b); }
+__device__ __forceinline__ T beta_rho(T a, T b) { return face_beta(a, b); }
 
 // f and the in-plane densities around an x-pair of one plane; the pair's own densities
 // (c) come from the z window the kernel keeps
@@ -208,30 +208,19 @@ __device__ __forceinline__ void load_pair_rho(PairRho<T>& R, const T* __restrict
   R.n = V2{in ? nv.x : inf, in ? nv.y : inf};
 }
 
-// coefficients of the even or odd cell of a pair from its densities and the pair's
-// densities on the planes below and above
-template <bool ODD, typename T>
-__device__ __forceinline__ Coef<T> cell_of_rho(const PairRho<T>& R, typename Vec2<T>::type below,
-                                               typename Vec2<T>::type above) {
-  Coef<T> C;
-  if (ODD) {
-    C.f = R.f.y;
-    C.xm = beta_rho(R.c.x, R.c.y);
-    C.xp = beta_rho(R.c.y, R.r);
-    C.ym = beta_rho(R.s.y, R.c.y);
-    C.yp = beta_rho(R.c.y, R.n.y);
-    C.zm = beta_rho(below.y, R.c.y);
-    C.zp = beta_rho(R.c.y, above.y);
-  } else {
-    C.f = R.f.x;
-    C.xm = beta_rho(R.l, R.c.x);
-    C.xp = beta_rho(R.c.x, R.c.y);
-    C.ym = beta_rho(R.s.x, R.c.x);
-    C.yp = beta_rho(R.c.x, R.n.x);
-    C.zm = beta_rho(below.x, R.c.x);
-    C.zp = beta_rho(R.c.x, above.x);
-  }
-  return C;
+// Both cells' coefficients of a pair from its plane's densities, every face once: zm
+// holds the pair's faces to the plane below (computed with that plane), `above` the
+// pair's densities on the plane above.  Returns the pair's faces to the plane above.
+template <typename T>
+__device__ __forceinline__ typename Vec2<T>::type pair_coef_rho(const PairRho<T>& R, typename Vec2<T>::type zm,
+                                                                typename Vec2<T>::type above, Coef<T>& even,
+                                                                Coef<T>& odd) {
+  using V2 = typename Vec2<T>::type;
+  const T x1 = beta_rho(R.c.x, R.c.y);
+  const V2 zp{beta_rho(R.c.x, above.x), beta_rho(R.c.y, above.y)};
+  even = Coef<T>{R.f.x, beta_rho(R.l, R.c.x), x1, beta_rho(R.s.x, R.c.x), beta_rho(R.c.x, R.n.x), zm.x, zp.x};
+  odd = Coef<T>{R.f.y, x1, beta_rho(R.c.y, R.r), beta_rho(R.s.y, R.c.y), beta_rho(R.c.y, R.n.y), zm.y, zp.y};
+  return zp;
 }
 
 // one cell's coefficients (the ring cells and the prologue)
@@ -387,7 +376,8 @@ __global__ __launch_bounds__(TX / 2 * TY) void k_rbgs_fused(const T* __restrict_
   int rr_, rc_, ri_, rj_;
   PairRaw<T> raw;        // both cells' coefficients of the plane above the current one
   PairRho<T> rraw;       // density form: the same plane's f and in-plane densities
-  V2 rc_lo, rc_hi;       // density form: the pair's densities on the current plane and two up
+  V2 rc_hi;              // density form: the pair's densities two planes up
+  V2 zlo;                // density form: the pair's faces between the current plane and the next
   Coef<T> black_cur;     // second colour's coefficients on the current plane
   T below0, below1;      // the pair's finished values on the plane under the current one
   {
@@ -406,9 +396,10 @@ __global__ __launch_bounds__(TX / 2 * TY) void k_rbgs_fused(const T* __restrict_
       pm2_1 = v.y;
     }
     if constexpr (RHO) {
-      rc_lo = load_centre(rt, po.c, k0, q);
+      const V2 rc0 = load_centre(rt, po.c, k0, q);
       load_pair_rho(rraw, f, rt, load_centre(rt, po.c, k0 + 1, q), po, k0 + 1, q);
       rc_hi = load_centre(rt, po.c, k0 + 2, q);
+      zlo = V2{beta_rho(rc0.x, rraw.c.x), beta_rho(rc0.y, rraw.c.y)};
     } else {
       load_pair(raw, f, bx, by, bz, po, k0 + 1, q);
     }
@@ -467,13 +458,19 @@ __global__ __launch_bounds__(TX / 2 * TY) void k_rbgs_fused(const T* __restrict_
       load_pair(raw_next, f, bx, by, bz, po, k + 2, q);
     }
     __syncthreads();
+    // both cells' coefficients on plane k+1: the first colour's now, the second's next step
+    Coef<T> red, black_next;
+    if constexpr (RHO) {
+      Coef<T> ev, od;
+      zlo = pair_coef_rho(rraw, zlo, rc_hi, ev, od);
+      red = ODD1 ? od : ev;
+      black_next = ODD1 ? ev : od;
+    } else {
+      red = cell_of<ODD1>(raw);
+      black_next = cell_of<!ODD1>(raw);
+    }
     if (k + 1 < n) {                   // first colour on plane k+1, tile and ring
       const int c = ct + ODD1;
-      Coef<T> red;
-      if constexpr (RHO)
-        red = cell_of_rho<ODD1>(rraw, rc_lo, rc_hi);
-      else
-        red = cell_of<ODD1>(raw);
       gs<T, W>(L[s1], rt_, c, at<T, W>(L[s0], rt_, c), at<T, W>(L[s2], rt_, c), red, h2, fs);
       if (has_ring) gs<T, W>(L[s1], rr_, rc_, at<T, W>(L[s0], rr_, rc_), at<T, W>(L[s2], rr_, rc_), ring_c, h2, fs);
     }
@@ -487,13 +484,11 @@ __global__ __launch_bounds__(TX / 2 * TY) void k_rbgs_fused(const T* __restrict_
       *reinterpret_cast<V2*>(reinterpret_cast<char*>(pout + (static_cast<long long>(k) << (2 * q))) + po.c) =
           V2{below0, below1};
     }
+    black_cur = black_next;
     if constexpr (RHO) {
-      black_cur = cell_of_rho<!ODD1>(rraw, rc_lo, rc_hi);
-      rc_lo = rraw.c;
       rraw = rraw_next;
       rc_hi = rc_next;
     } else {
-      black_cur = cell_of<!ODD1>(raw);
       raw = raw_next;
     }
   };

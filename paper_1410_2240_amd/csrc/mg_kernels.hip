@@ -115,10 +115,10 @@ __device__ __forceinline__ PairFaces<T> pair_faces(const T* __restrict__ bx, con
 // from the cell density: rt holds rho on active cells and +inf on every other cell,
 // and a neighbour beyond a z wall counts as +inf too.  beta = 2 / (rt_L + rt_R) is then
 // 0 on every face that touches an inactive cell or a wall, and on open faces it is bit
-// for bit the stored coefficient (the sum is commutative and the division correctly
-// rounded).  A sweep then reads one density instead of three face arrays.
+// for bit the stored coefficient (the sum is commutative, and both are formed by
+// face_beta).  A sweep then reads one density instead of three face arrays.
 template <typename T>
-__device__ __forceinline__ T beta_rho(T a, T b) { return T(2) / (a + b); }
+__device__ __forceinline__ T beta_rho(T a, T b) { return face_beta(a, b); }
 
 template <typename T>
 __device__ __forceinline__ PairFaces<T> pair_faces_rho(const T* __restrict__ rt, int i, int j, int k, int q) {
@@ -205,9 +205,9 @@ __global__ __launch_bounds__(kBlock) void k_coeffs_from_rho(const double* __rest
     bz[c] = oz ? 1.0 : 0.0;
     return;
   }
-  bx[c] = ox ? 2.0 / (rho[c] + rho[cx]) : 0.0;
-  by[c] = oy ? 2.0 / (rho[c] + rho[cy]) : 0.0;
-  bz[c] = oz ? 2.0 / (rho[c] + rho[cz]) : 0.0;
+  bx[c] = ox ? face_beta(rho[c], rho[cx]) : 0.0;
+  by[c] = oy ? face_beta(rho[c], rho[cy]) : 0.0;
+  bz[c] = oz ? face_beta(rho[c], rho[cz]) : 0.0;
 }
 
 // Density moved cell centre to cell centre: mean over the active children, 1 when
@@ -248,9 +248,9 @@ __global__ __launch_bounds__(kBlock) void k_area_to_beta(const double* __restric
   const int c = static_cast<int>(t);
   const int i = c & m, j = (c >> q) & m, k = c >> (2 * q);
   const double ax = bx[c], ay = by[c], az = bz[c];
-  if (ax != 0.0) bx[c] = ax * (2.0 / (rho[c] + rho[cell((i - 1) & m, j, k, q)]));
-  if (ay != 0.0) by[c] = ay * (2.0 / (rho[c] + rho[cell(i, (j - 1) & m, k, q)]));
-  if (az != 0.0) bz[c] = az * (2.0 / (rho[c] + rho[c - (1 << (2 * q))]));
+  if (ax != 0.0) bx[c] = ax * face_beta(rho[c], rho[cell((i - 1) & m, j, k, q)]);
+  if (ay != 0.0) by[c] = ay * face_beta(rho[c], rho[cell(i, (j - 1) & m, k, q)]);
+  if (az != 0.0) bz[c] = az * face_beta(rho[c], rho[c - (1 << (2 * q))]);
 }
 
 // Close the finest faces (copy unless bx is null), validate them, mark active cells.
