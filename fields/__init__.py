@@ -124,6 +124,30 @@ def body_mask_slab(N: int, k: int, centre) -> np.ndarray:
     return (q >= 1.0).astype(np.uint8)
 
 
+def body_psi_corners(N: int, centre, axes=BODY_SEMI_AXES) -> np.ndarray:
+    """The body as a level set at the cell corners (i h, j h, k h), k = 0..N, shape
+    (N+1, N, N): psi = (|(x - c) / a| - 1) min(a), positive in the fluid, negative in
+    the body, zero on the ellipsoid (the paper builds psi from hull panels; an
+    analytic ellipsoid stands in)."""
+    g = np.arange(N) / N
+    gz = np.arange(N + 1) / N
+    q = (((g[None, None, :] - centre[0]) / axes[0]) ** 2 + ((g[None, :, None] - centre[1]) / axes[1]) ** 2
+         + ((gz[:, None, None] - centre[2]) / axes[2]) ** 2)
+    return (np.sqrt(q) - 1.0) * min(axes)
+
+
+def wavy_cut(N: int):
+    """The wavy-interface field with the ellipsoid as a cut-cell body: (rho, psi).
+    rho comes from the interface everywhere (cut cells hold fluid); psi at corners."""
+    x = centres(N)
+    zs = wavy_surface(x[None, :], x[:, None])
+    zc = float(wavy_surface(np.array(0.5), np.array(0.5)))
+    h = 1.0 / N
+    z = centres(N)[:, None, None]
+    rho = density_from_phi(0.5 * (1.0 - np.tanh((z - zs[None]) / (2.0 * h))))
+    return rho, body_psi_corners(N, (0.5, 0.5, zc))
+
+
 # ---------------------------------------------------------------- right-hand side
 
 def _velocity_slab(field: int, index: int, N: int) -> np.ndarray:
