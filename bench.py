@@ -171,6 +171,7 @@ def main():
         del mgp
         torch.cuda.empty_cache()
     log(f"coarsening ablation {abl}")
+    cut = cut_cell_leg(N, args) if args.config == "c2" else None
     traffic = recorded_traffic(inp.name, N)
     out = {
         "metric": "grid-pts/s per V-cycle (FP64 projection: setup + solve to 1e-10)",
@@ -188,6 +189,7 @@ def main():
         "status": {"fp64": st64, "mixed": stmx},
         "krylov_fcg": kr,
         "coarsening_ablation": abl,
+        "cut_cells": cut,
         "vcycle_ms": {"fp64": vc64, "fp32": vc32},
         "vcycle_pts_per_s": {"fp64": n / (vc64 * 1e-3), "fp32": n / (vc32 * 1e-3)},
         # algorithmic scalars per finest cell per V(2,2) cycle: the FP64 finest grid reads
@@ -204,6 +206,43 @@ def main():
         log("timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(inp)
     print(json.dumps(out), flush=True)
+
+
+def cut_cell_leg(N, args):
+    """The same wavy field with the ellipsoid as a cut-cell body (section 2.2): time to
+    build fractions, merge map and coefficients, and a flexible-CG solve to tol."""
+    import torch
+    import fields
+    from paper_1410_2240_amd import MG
+    from paper_1410_2240_amd.cutcell import cut_cells, cut_coeffs, merge_fill, merge_rhs
+    rho_np, psi_np = fields.wavy_cut(N)
+    rho = torch.from_numpy(rho_np).cuda()
+    psi = torch.from_numpy(psi_np).cuda()
+    del rho_np, psi_np
+    geo = cut_cells(psi, 8)
+    torch.cuda.synchronize()
+    a, b, c = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    a.record()
+    geo = cut_cells(psi, 8)
+    b.record()
+    bx, by, bz, mask = cut_coeffs(rho, *geo)
+    c.record()
+    torch.cuda.synchronize()
+    vol, merge_to = geo[3], geo[4]
+    g = torch.Generator(device="cuda").manual_seed(1410)
+    f = merge_rhs(merge_to, torch.randn(rho.shape, dtype=torch.float64, device="cuda", generator=g))
+    torch.cuda.synchronize()
+    t0 = time.time()
+    mg = MG(bx, by, bz, mask, krylov=True)
+    p, hist, st = mg.solve(f, tol=args.tol, max_cycles=args.max_cycles, raise_on_fail=False)
+    merge_fill(merge_to, p)
+    torch.cuda.synchronize()
+    out = {"cut_cells_ms": a.elapsed_time(b), "cut_coeffs_ms": b.elapsed_time(c),
+           "cut_cells": int(((vol > 0) & (vol < 1)).sum()), "merged_cells": int((merge_to >= 0).sum()),
+           "fcg_steps": st["cycles"], "fcg_status": st["status"], "final_relres": hist[-1],
+           "setup_plus_solve_ms": (time.time() - t0) * 1e3, "rhs": "P(N(0,1)) merged"}
+    log(f"cut cells {out}")
+    return out
 
 
 def recorded_traffic(workload, N):

@@ -176,6 +176,42 @@ int mg_divergence(mg_ctx* ctx, const double* ux, const double* uy, const double*
 int mg_project(mg_ctx* ctx, double* ux, double* uy, double* uz,
                const double* rx, const double* ry, const double* rz, double dt, const double* p);
 
+/*
+ * Cut cells (section 2.2: the body as a signed distance psi, positive in the fluid;
+ * finite volumes with the open fraction of each face, eq. (integral2); cells under a
+ * quarter full merged with a neighbour along the steepest gradient of psi).  These
+ * build the coefficients and the mask that mg_setup takes; the paper leaves the
+ * formulas to a reference, so the library fixes this reading:
+ *
+ *   mg_cut_cells:  psi (DEVICE, [N+1][N][N]) holds psi at the cell corners (i h, j h, k h),
+ *     k = 0..N, x and y periodic.  ax, ay, az ([N][N][N], low-face storage) receive the
+ *     open-area fraction of each face: the fraction of samples x samples midpoint
+ *     samples of the bilinear interpolant of the face's corners where psi > 0 (az on
+ *     the bottom wall is 0).  vol receives the fluid fraction of each cell from
+ *     samples^3 samples of the trilinear interpolant.  merge_to receives, for each cell
+ *     with 0 < vol < 1/4, the flat index (k N + j) N + i of the face neighbour it merges
+ *     into: along the largest component of the gradient of the trilinear psi at the cell
+ *     centre (ties x, y, z), on the side where psi grows, provided that cell lies inside
+ *     the z walls and has vol >= 1/4; -1 everywhere else.  samples is 2, 4, 8 or 16.
+ *     Sample values are summed in a fixed order without fused multiply-adds, so every
+ *     inside/outside decision is reproducible bit for bit.
+ *   mg_cut_coeffs:  bx, by, bz = open area x 2/(rho_L + rho_R) on faces between two kept
+ *     cells (vol > 0 and not merged away), else 0; mask = kept.  A face between two
+ *     donors that merge side by side (same direction) into face-neighbour targets adds
+ *     its area to the face between the targets; other donor faces are dropped.
+ *   mg_merge_rhs:  f_merged = f plus, on each target, the sources of its donors; 0 on
+ *     donors (call before mg_solve).
+ *   mg_merge_fill:  after the solve, p on each donor = p on its target (in place).
+ * All are stream-ordered on hip_stream and return MG_EINVAL for bad dims or pointers.
+ */
+int mg_cut_cells(const double* psi, const int dims[3], int samples, double* ax, double* ay, double* az,
+                 double* vol, int32_t* merge_to, void* hip_stream);
+int mg_cut_coeffs(const double* rho, const double* ax, const double* ay, const double* az, const double* vol,
+                  const int32_t* merge_to, const int dims[3], double* bx, double* by, double* bz, uint8_t* mask,
+                  void* hip_stream);
+int mg_merge_rhs(const int32_t* merge_to, const double* f, double* f_merged, const int dims[3], void* hip_stream);
+int mg_merge_fill(const int32_t* merge_to, double* p, const int dims[3], void* hip_stream);
+
 void mg_destroy(mg_ctx* ctx);
 
 /* Thread-local message describing the last failure on this thread ("" if none). */

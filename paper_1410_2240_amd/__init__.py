@@ -6,3 +6,4 @@ arguments.  See include/mg.h for the ABI.
 """
 from .solver import MG, MGError, coeffs_from_rho, workspace_size  # noqa: F401
 from .autograd import PoissonSolve, poisson_solve  # noqa: F401
+from . import cutcell  # noqa: F401

@@ -47,6 +47,10 @@ SIGNATURES = {
     "mg_coeff_grad": (_I, [_P, _P, _P, _I, _P, _P, _P, _P]),
     "mg_divergence": (_I, [_P, _P, _P, _P, _P, _P, _P, _D, _P]),
     "mg_project": (_I, [_P, _P, _P, _P, _P, _P, _P, _D, _P]),
+    "mg_cut_cells": (_I, [_P, _DIMS, _I, _P, _P, _P, _P, _P, _P]),
+    "mg_cut_coeffs": (_I, [_P, _P, _P, _P, _P, _P, _DIMS, _P, _P, _P, _P, _P]),
+    "mg_merge_rhs": (_I, [_P, _P, _P, _DIMS, _P]),
+    "mg_merge_fill": (_I, [_P, _P, _DIMS, _P]),
     "mg_destroy": (None, [_P]),
     "mg_last_error": (ctypes.c_char_p, []),
     "mg_level_info": (_I, [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_D)]),

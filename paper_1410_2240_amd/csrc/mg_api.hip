@@ -569,6 +569,54 @@ int mg_setup(mg_ctx** out, void* workspace, size_t ws_bytes, const double* bx, c
   return setup_impl(out, workspace, ws_bytes, bx, by, bz, nullptr, mask, dims, h, flags, hip_stream);
 }
 
+int mg_cut_cells(const double* psi, const int dims[3], int samples, double* ax, double* ay, double* az,
+                 double* vol, int32_t* merge_to, void* hip_stream) {
+  int n = 0;
+  if (mg::validate_dims(dims, &n) != 0) return fail(MG_EINVAL, "dims must be equal powers of two in [8, 1024]");
+  if (!psi || !ax || !ay || !az || !vol || !merge_to) return fail(MG_EINVAL, "null array pointer");
+  if (samples != 2 && samples != 4 && samples != 8 && samples != 16)
+    return fail(MG_EINVAL, "samples must be 2, 4, 8 or 16 (got %d)", samples);
+  int q = 0;
+  while ((1 << q) < n) ++q;
+  MG_HIP(mg::launch_cut_cells(psi, q, samples, ax, ay, az, vol, merge_to, static_cast<hipStream_t>(hip_stream)));
+  return MG_OK;
+}
+
+int mg_cut_coeffs(const double* rho, const double* ax, const double* ay, const double* az, const double* vol,
+                  const int32_t* merge_to, const int dims[3], double* bx, double* by, double* bz, uint8_t* mask,
+                  void* hip_stream) {
+  int n = 0;
+  if (mg::validate_dims(dims, &n) != 0) return fail(MG_EINVAL, "dims must be equal powers of two in [8, 1024]");
+  if (!rho || !ax || !ay || !az || !vol || !merge_to || !bx || !by || !bz || !mask)
+    return fail(MG_EINVAL, "null array pointer");
+  int q = 0;
+  while ((1 << q) < n) ++q;
+  MG_HIP(mg::launch_cut_coeffs(rho, ax, ay, az, vol, merge_to, q, bx, by, bz, mask,
+                               static_cast<hipStream_t>(hip_stream)));
+  return MG_OK;
+}
+
+int mg_merge_rhs(const int32_t* merge_to, const double* f, double* f_merged, const int dims[3], void* hip_stream) {
+  int n = 0;
+  if (mg::validate_dims(dims, &n) != 0) return fail(MG_EINVAL, "dims must be equal powers of two in [8, 1024]");
+  if (!merge_to || !f || !f_merged) return fail(MG_EINVAL, "null array pointer");
+  if (f == f_merged) return fail(MG_EINVAL, "f_merged must not alias f");
+  int q = 0;
+  while ((1 << q) < n) ++q;
+  MG_HIP(mg::launch_merge_rhs(merge_to, f, f_merged, q, static_cast<hipStream_t>(hip_stream)));
+  return MG_OK;
+}
+
+int mg_merge_fill(const int32_t* merge_to, double* p, const int dims[3], void* hip_stream) {
+  int n = 0;
+  if (mg::validate_dims(dims, &n) != 0) return fail(MG_EINVAL, "dims must be equal powers of two in [8, 1024]");
+  if (!merge_to || !p) return fail(MG_EINVAL, "null array pointer");
+  int q = 0;
+  while ((1 << q) < n) ++q;
+  MG_HIP(mg::launch_merge_fill(merge_to, p, q, static_cast<hipStream_t>(hip_stream)));
+  return MG_OK;
+}
+
 int mg_setup_from_rho(mg_ctx** out, void* workspace, size_t ws_bytes, const double* rho, const uint8_t* mask,
                       const int dims[3], double h, int flags, void* hip_stream) {
   if (!rho) return fail(MG_EINVAL, "null density pointer");

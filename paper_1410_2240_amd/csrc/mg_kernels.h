@@ -48,6 +48,21 @@ hipError_t launch_coarsen(const double* bx, const double* by, const double* bz, 
                           int qc, double* cbx, double* cby, double* cbz, uint8_t* cmask, hipStream_t s);
 hipError_t launch_to_f32(const double* src, float* dst, long long count, hipStream_t s);
 
+// ---- cut cells (setup) ---------------------------------------------------------
+// Cells with 0 < fluid fraction < kMergeFraction merge with a neighbour.
+constexpr double kMergeFraction = 0.25;
+// psi at corners [(N+1)][N][N] -> open-area fractions (low faces), fluid fractions and
+// the merge map (flat target index or -1); samples per direction is a power of two
+hipError_t launch_cut_cells(const double* psi, int q, int samples, double* ax, double* ay, double* az, double* vol,
+                            int32_t* merge_to, hipStream_t s);
+// face coefficients of the merged cut-cell operator and its activity mask
+hipError_t launch_cut_coeffs(const double* rho, const double* ax, const double* ay, const double* az,
+                             const double* vol, const int32_t* merge_to, int q, double* bx, double* by, double* bz,
+                             uint8_t* mask, hipStream_t s);
+// g = f with the donors' sources moved onto their targets; p on donors = p on targets
+hipError_t launch_merge_rhs(const int32_t* merge_to, const double* f, double* g, int q, hipStream_t s);
+hipError_t launch_merge_fill(const int32_t* merge_to, double* p, int q, hipStream_t s);
+
 // ---- V-cycle steps (T = double or float) ----------------------------------------
 // fshift: device scalar subtracted from f on active cells (nullptr = none)
 template <typename T>
