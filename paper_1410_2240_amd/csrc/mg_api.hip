@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "mg.h"
@@ -148,6 +149,12 @@ template <typename T>
 int residual_restrict(mg_ctx* c, int l, const T* p, const T* f, const double* fshift, T* fc, T* ec) {
   const Level& a = c->lv[l];
   const View<T> v = c->view<T>(l);
+  if constexpr (std::is_same<T, double>::value) {
+    if (mg::march_supported(a.q)) {
+      MG_HIP(mg::launch_residual_restrict_march(p, f, v.bx, v.by, v.bz, v.rt, a.q, a.h, fshift, fc, ec, c->stream));
+      return MG_OK;
+    }
+  }
   MG_HIP(mg::launch_residual_restrict<T>(p, f, v.bx, v.by, v.bz, v.rt, a.q, a.h, fshift, fc, ec, c->stream));
   return MG_OK;
 }
@@ -205,8 +212,12 @@ int residual_norm(mg_ctx* c, const double* p, const double* f, const double* fsh
                   double* r64 = nullptr, double* z64 = nullptr) {
   const Level& a = c->lv[0];
   int nb = 0;
-  MG_HIP(mg::launch_residual_norm(p, f, a.bx, a.by, a.bz, a.rt, a.q, a.h, fshift, r32, e32, r64, z64, c->partials, &nb,
-                                  c->stream));
+  if (mg::march_supported(a.q))
+    MG_HIP(mg::launch_residual_norm_march(p, f, a.bx, a.by, a.bz, a.rt, a.q, a.h, fshift, r32, e32, r64, z64,
+                                          c->partials, &nb, c->stream));
+  else
+    MG_HIP(mg::launch_residual_norm(p, f, a.bx, a.by, a.bz, a.rt, a.q, a.h, fshift, r32, e32, r64, z64, c->partials,
+                                    &nb, c->stream));
   return reduce(c, nb, 1.0, S_RNORM2);
 }
 
@@ -277,7 +288,12 @@ int solve_one(mg_ctx* c, const double* f, double* p, double tol, int max_cycles,
     }
     while (std::isfinite(r) && r > tol && *cycles < max_cycles) {
       int nb = 0;
-      MG_HIP(mg::launch_fcg_aw(kd, kr, a.bx, a.by, a.bz, a.rt, q, a.h, kw, part(c, 0), part(c, 1), &nb, c->stream));
+      if (mg::march_supported(q))
+        MG_HIP(mg::launch_fcg_aw_march(kd, kr, a.bx, a.by, a.bz, a.rt, q, a.h, kw, part(c, 0), part(c, 1), &nb,
+                                       c->stream));
+      else
+        MG_HIP(mg::launch_fcg_aw(kd, kr, a.bx, a.by, a.bz, a.rt, q, a.h, kw, part(c, 0), part(c, 1), &nb,
+                                 c->stream));
       MG_TRY(reduce_set(c, 0, nb, S_DW));
       MG_TRY(reduce_set(c, 1, nb, S_DR));
       MG_HIP(mg::launch_fcg_update(p, kr, kd, kw, c->scal + S_DR, c->scal + S_DW, q, mixed ? nullptr : kz,

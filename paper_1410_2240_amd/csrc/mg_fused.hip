@@ -26,6 +26,7 @@
 // wherever a face touches an inactive cell or a wall and otherwise bit for bit the
 // stored coefficient.  That is 4 scalars per cell per sweep instead of 6, for nine
 // reciprocals per x-pair and plane (each face once).
+#include "mg_buffer.h"
 #include "mg_kernels.h"
 
 #include <type_traits>
@@ -34,56 +35,12 @@ namespace mg {
 
 namespace {
 
-template <typename T>
-struct Vec2;
-template <>
-struct Vec2<double> {
-  using type = double2;
-};
-template <>
-struct Vec2<float> {
-  using type = float2;
-};
-
-// Addressing.  A workgroup marches up z, so each load of a step reads one plane of an
-// array.  The plane is a buffer resource (a descriptor in scalar registers, the same for
-// the whole workgroup) and each thread keeps 32-bit byte offsets in the plane, computed
-// once (N <= 1024: a plane is at most 8 MiB).  A plane outside the grid gets a record
-// count of 0, so every load from it returns 0 without a branch.
-using Rsrc = __amdgpu_buffer_rsrc_t;
-constexpr int kBufferWord3 = 0x00020000;   // raw 32-bit-dword buffer, range-checked (gfx9)
-
-template <typename T>
-__device__ __forceinline__ Rsrc plane_rsrc(const T* a, int kk, int q) {
-  const int k = __builtin_amdgcn_readfirstlane(kk);   // uniform: keeps the descriptor scalar
-  const bool in = k >= 0 && k < (1 << q);
-  const T* base = a + (static_cast<long long>(in ? k : 0) << (2 * q));
-  const int bytes = in ? static_cast<int>(sizeof(T)) << (2 * q) : 0;
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base), static_cast<short>(0), bytes, kBufferWord3);
-}
-template <typename T>
-__device__ __forceinline__ unsigned off_of(int i, int j, int q) {
-  const int m = (1 << q) - 1;
-  return static_cast<unsigned>(((j & m) << q) | (i & m)) * static_cast<unsigned>(sizeof(T));
-}
-__device__ __forceinline__ double ld1(Rsrc r, unsigned off, double) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
-}
-__device__ __forceinline__ float ld1(Rsrc r, unsigned off, float) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
-}
-__device__ __forceinline__ double2 ld2(Rsrc r, unsigned off, double) {
-  const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
-  double2 d;
-  __builtin_memcpy(&d, &v, sizeof d);
-  return d;
-}
-__device__ __forceinline__ float2 ld2(Rsrc r, unsigned off, float) {
-  const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
-  float2 d;
-  __builtin_memcpy(&d, &v, sizeof d);
-  return d;
-}
+using buf::Vec2;
+using buf::Rsrc;
+using buf::plane_rsrc;
+using buf::off_of;
+using buf::ld1;
+using buf::ld2;
 
 // in-plane byte offsets around a thread's x-pair (i even, i+1) in row j
 struct PairOffsets {

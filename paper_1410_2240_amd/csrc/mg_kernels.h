@@ -106,6 +106,21 @@ struct CoarseCycle {
 template <typename T>
 hipError_t launch_coarse_cycle(const CoarseCycle<T>& a, hipStream_t s);
 
+// ---- z-marching FP64 residual passes (grids of 32^3 and up) ------------------------
+// Same results as the grid-stride kernels below (per cell), each plane of p and of the
+// coefficients read once per column; rt != nullptr selects the density form.
+int march_supported(int q);
+hipError_t launch_residual_norm_march(const double* p, const double* f, const double* bx, const double* by,
+                                      const double* bz, const double* rt, int q, double h, const double* fshift,
+                                      float* r32, float* e32, double* r64, double* z64, double* partials,
+                                      int* nblocks, hipStream_t s);
+hipError_t launch_residual_restrict_march(const double* p, const double* f, const double* bx, const double* by,
+                                          const double* bz, const double* rt, int q, double h, const double* fshift,
+                                          double* fc, double* ec, hipStream_t s);
+hipError_t launch_fcg_aw_march(const double* d, const double* r, const double* bx, const double* by, const double* bz,
+                               const double* rt, int q, double h, double* w, double* part_dw, double* part_dr,
+                               int* nblocks, hipStream_t s);
+
 // ---- FP64 finest-grid passes ------------------------------------------------------
 // partials[blockIdx] = sum over active cells of r^2, r = (f - fshift) - A p; optional
 // r32 = float(r) and e32 = 0 (mixed-precision refinement); returns the block count used.
