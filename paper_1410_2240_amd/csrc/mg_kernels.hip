@@ -503,53 +503,108 @@ __global__ __launch_bounds__(64) void k_coarse_solve(const T* __restrict__ f, T*
 
 // The whole V(2,2) sub-cycle on grids of 16^3 and smaller, by one workgroup: the same
 // per-cell steps as the multi-block kernels, separated by workgroup barriers instead of
-// kernel launches.  Level 0 of `a` enters with its right-hand side and a zero correction.
-// The level loops are unrolled over the at most three grids (16^3, 8^3, 4^3) so every
-// field of `a` is read with a constant index.
+// kernel launches.  The corrections and right-hand sides of every grid live in LDS
+// (75 KB in FP64 for 16^3 + 8^3 + 4^3); only the coefficients and masks are read from
+// memory.  Level 0 of `a` enters with its right-hand side and its correction (zero, or
+// the current iterate when it is the finest grid) and gets the result back.  The level
+// loops are unrolled over the at most three grids so every field of `a` is read with a
+// constant index.
 constexpr int kCoarseThreads = 512;
+constexpr int kCoarseCells = 4096 + 512 + 64;
+
+// e = A_c^+ (f - active mean of f) on the 4^3 grid in FP64 by the whole block: the mean
+// by the first wavefront, then each row of the pseudo-inverse product by 8 threads.
+template <typename T>
+__device__ __forceinline__ void coarse_solve_block(const T* f, T* e, const double* __restrict__ pinv,
+                                                   const uint8_t* __restrict__ mask, double* fh) {
+  const int t = threadIdx.x;
+  if (t < 64) {
+    const bool act = mask[t] != 0;
+    const double v = act ? static_cast<double>(f[t]) : 0.0;
+    double s = v, cnt = act ? 1.0 : 0.0;
+    for (int off = 32; off > 0; off >>= 1) {
+      s += __shfl_xor(s, off, 64);
+      cnt += __shfl_xor(cnt, off, 64);
+    }
+    const double mean = cnt > 0.0 ? s / cnt : 0.0;
+    fh[t] = act ? v - mean : 0.0;
+  }
+  const int row = t >> 3, part = t & 7;
+  double pv[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) pv[c] = pinv[row * 64 + part * 8 + c];   // issued before the barrier
+  __syncthreads();
+  double acc = 0.0;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) acc = __builtin_fma(pv[c], fh[part * 8 + c], acc);
+  acc += __shfl_xor(acc, 1, 64);
+  acc += __shfl_xor(acc, 2, 64);
+  acc += __shfl_xor(acc, 4, 64);
+  if (part == 0) e[row] = static_cast<T>(acc);
+}
 
 template <typename T>
 __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle(CoarseCycle<T> a) {
+  static_assert(kCoarseThreads == 512, "the pseudo-inverse product maps 64 rows x 8 threads");
   __shared__ double fh[64];
+  __shared__ T se[kCoarseCells];
+  __shared__ T sf[kCoarseCells];
   const int tid = threadIdx.x;
   const int last = a.nlev - 1;
-  auto sweep = [&](int l, int colour) {
+  // LDS arrays of each grid
+  T* e[3];
+  T* f[3];
+  {
+    int off = 0;
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      e[l] = se + off;
+      f[l] = sf + off;
+      if (l < a.nlev) off += 1 << (3 * a.q[l]);
+    }
+  }
+  const int n0 = 1 << (3 * a.q[0]);
+  for (int c = tid; c < n0; c += kCoarseThreads) {
+    e[0][c] = a.e[0][c];
+    f[0][c] = a.f[0][c];
+  }
+  __syncthreads();
+  auto sweep = [&](int l, int colour, const T* bx, const T* by, const T* bz) {
     const T fs = (l == 0 && a.fshift) ? static_cast<T>(*a.fshift) : T(0);
     for (int pr = tid; pr < (1 << (3 * a.q[l] - 1)); pr += kCoarseThreads)
-      gs_pair(a.e[l], a.f[l], a.bx[l], a.by[l], a.bz[l], a.q[l], a.h2[l], colour, fs, pr);
+      gs_pair(e[l], f[l], bx, by, bz, a.q[l], a.h2[l], colour, fs, pr);
     __syncthreads();
   };
 #pragma unroll
   for (int l = 0; l < 2; ++l) {
     if (l < last) {
       for (int s = 0; s < 2; ++s) {
-        sweep(l, 0);
-        sweep(l, 1);
+        sweep(l, 0, a.bx[l], a.by[l], a.bz[l]);
+        sweep(l, 1, a.bx[l], a.by[l], a.bz[l]);
       }
       const T fs = (l == 0 && a.fshift) ? static_cast<T>(*a.fshift) : T(0);
       for (int C = tid; C < (1 << (3 * (a.q[l] - 1))); C += kCoarseThreads)
-        restrict_cell<T, false>(a.e[l], a.f[l], Coefs<T>{a.bx[l], a.by[l], a.bz[l], nullptr}, a.q[l], a.inv_h2[l], fs,
-                                a.f[l + 1], a.e[l + 1], C);
+        restrict_cell<T, false>(e[l], f[l], Coefs<T>{a.bx[l], a.by[l], a.bz[l], nullptr}, a.q[l], a.inv_h2[l], fs,
+                                f[l + 1], e[l + 1], C);
       __syncthreads();
     }
   }
-  const T* fl = last == 0 ? a.f[0] : (last == 1 ? a.f[1] : a.f[2]);
-  T* el = last == 0 ? a.e[0] : (last == 1 ? a.e[1] : a.e[2]);
   const uint8_t* ml = last == 0 ? a.mask[0] : (last == 1 ? a.mask[1] : a.mask[2]);
-  coarse_solve_wave(fl, el, a.pinv, ml, fh);
+  coarse_solve_block(f[last], e[last], a.pinv, ml, fh);
   __syncthreads();
 #pragma unroll
   for (int l = 1; l >= 0; --l) {
     if (l < last) {
       for (int C = tid; C < (1 << (3 * (a.q[l] - 1))); C += kCoarseThreads)
-        prolong_cell(a.e[l + 1], a.e[l], a.mask[l], a.q[l], C);
+        prolong_cell(e[l + 1], e[l], a.mask[l], a.q[l], C);
       __syncthreads();
       for (int s = 0; s < 2; ++s) {
-        sweep(l, 1);
-        sweep(l, 0);
+        sweep(l, 1, a.bx[l], a.by[l], a.bz[l]);
+        sweep(l, 0, a.bx[l], a.by[l], a.bz[l]);
       }
     }
   }
+  for (int c = tid; c < n0; c += kCoarseThreads) a.e[0][c] = e[0][c];
 }
 
 // ------------------------------------------------------------------ FP64 finest passes
