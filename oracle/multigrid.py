@@ -225,6 +225,20 @@ def fp32_levels(hier: Hierarchy):
     return [lev.astype(np.float32) for lev in hier.levels]
 
 
+def fp32_density_level(rho, lev: Level) -> Level:
+    """The finest FP32 grid formed from the density in single precision: rho32 = fl32(rho)
+    on active cells (+inf elsewhere), beta32 = 2 / (rho32_L + rho32_R) in float32 (0 on
+    faces touching an inactive cell and on the bottom wall).  This is the operator of
+    FP32 cycles that work from the density rather than rounding the FP64 coefficients."""
+    r = np.where(lev.mask, np.asarray(rho, np.float64), np.inf).astype(np.float32)
+    two = np.float32(2.0)
+    bx = two / (r + np.roll(r, 1, axis=2))
+    by = two / (r + np.roll(r, 1, axis=1))
+    bz = np.zeros_like(r)
+    bz[1:] = two / (r[1:] + r[:-1])
+    return Level(bx, by, bz, lev.mask.copy(), lev.h)
+
+
 def solve_mixed(hier: Hierarchy, f, p0=None, tol: float = 1e-10, max_steps: int = 100):
     """FP64 iterative refinement with one FP32 V-cycle per step (coarsest solve FP64)."""
     lev = hier.fine

@@ -62,6 +62,7 @@ struct Level {
   double h = 0;
   double *bx = nullptr, *by = nullptr, *bz = nullptr, *f = nullptr, *e = nullptr, *t = nullptr;
   double* rt = nullptr;   // finest grid of a hierarchy built from rho: the density form
+  float* rt32 = nullptr;  // the same in FP32 (mixed contexts, grids swept in one pass)
   uint8_t* mask = nullptr;
   float *bx32 = nullptr, *by32 = nullptr, *bz32 = nullptr, *f32 = nullptr, *e32 = nullptr, *t32 = nullptr;
 };
@@ -95,7 +96,7 @@ struct mg_ctx {
   }
   View<float> v32(int l) const {
     const Level& a = lv[l];
-    return {a.bx32, a.by32, a.bz32, a.f32, a.e32, a.t32, nullptr};
+    return {a.bx32, a.by32, a.bz32, a.f32, a.e32, a.t32, a.rt32};
   }
   template <typename T>
   View<T> view(int l) const;
@@ -498,6 +499,12 @@ int setup_impl(mg_ctx** out, void* workspace, size_t ws_bytes, const double* bx,
     // of the three face arrays
     f0.rt = at<double>(c->ws, plan.lv[0].rt);
     hip(mg::launch_rho_tilde(rho, f0.mask, f0.q, f0.rt, s), "rho_tilde");
+    if ((flags & MG_MIXED) && mg::fused_sweep_supported(f0.q)) {
+      // the FP32 cycles form their finest faces from an FP32 copy (one-pass sweep grids,
+      // so that smoother and residual use the same FP32 operator)
+      f0.rt32 = at<float>(c->ws, plan.lv[0].rt32);
+      hip(mg::launch_to_f32(f0.rt, f0.rt32, cells(f0), s), "to_f32(rt)");
+    }
   }
   for (int l = 1; l < c->L; ++l) {
     const Level& a = c->lv[l - 1];

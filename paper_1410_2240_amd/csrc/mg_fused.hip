@@ -474,12 +474,10 @@ hipError_t launch_tx(const T* pin, T* pout, const T* f, const T* bx, const T* by
   const T h2 = static_cast<T>(h * h);
   const int first = order == 0 ? 0 : 1;   // pre-smoothing: red first; post-smoothing: black first
   const dim3 grid(static_cast<unsigned>(blocks));
-  if constexpr (std::is_same<T, double>::value) {
-    if (rt) {
-      hipLaunchKernelGGL((k_rbgs_fused<T, TX, TY, true>), grid, dim3(threads), 0, s, pin, pout, f, bx, by, bz, rt, q, kc,
-                         h2, first, fshift);
-      return hipGetLastError();
-    }
+  if (rt) {
+    hipLaunchKernelGGL((k_rbgs_fused<T, TX, TY, true>), grid, dim3(threads), 0, s, pin, pout, f, bx, by, bz, rt, q, kc,
+                       h2, first, fshift);
+    return hipGetLastError();
   }
   hipLaunchKernelGGL((k_rbgs_fused<T, TX, TY, false>), grid, dim3(threads), 0, s, pin, pout, f, bx, by, bz, rt, q, kc, h2,
                      first, fshift);
@@ -495,7 +493,6 @@ hipError_t launch_rbgs_fused(const T* pin, T* pout, const T* f, const T* bx, con
                              int q, double h, int order, const double* fshift, hipStream_t s) {
   const int n = 1 << q;
   if (n < 64) return hipErrorInvalidValue;
-  if (!std::is_same<T, double>::value && rt) return hipErrorInvalidValue;   // density form is FP64 only
   if (n == 64) return launch_tx<T, 64, 8>(pin, pout, f, bx, by, bz, rt, q, h, order, fshift, s);
   if (n == 128) return launch_tx<T, 128, 8>(pin, pout, f, bx, by, bz, rt, q, h, order, fshift, s);
   return launch_tx<T, 128, 16>(pin, pout, f, bx, by, bz, rt, q, h, order, fshift, s);

@@ -27,6 +27,16 @@ __device__ __forceinline__ double face_beta(double a, double b) {
   return __builtin_isinf(s) ? 0.0 : 2.0 * r;
 }
 
+// The FP32 face product of the mixed-precision cycles' density form: the FP32
+// reciprocal and one Newton step (within about an ulp of the rounded FP32 quotient).
+__device__ __forceinline__ float face_beta(float a, float b) {
+  const float s = a + b;
+  float r = __builtin_amdgcn_rcpf(s);
+  const float e = __builtin_fmaf(-s, r, 1.0f);
+  r = __builtin_fmaf(r, e, r);
+  return __builtin_isinf(s) ? 0.0f : 2.0f * r;
+}
+
 // ---- setup --------------------------------------------------------------------
 // beta_f = o_f 2/(rho_L + rho_R); with rho == nullptr the open-face areas o_f (0 or 1)
 hipError_t launch_coeffs_from_rho(const double* rho, const uint8_t* mask, int q,

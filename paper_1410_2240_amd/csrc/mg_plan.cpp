@@ -64,6 +64,7 @@ int build_plan(int n, int flags, Plan* plan) {
       lv.f32 = c.take(cells * 4);   // level 0: the FP32 residual of each refinement step
       lv.e32 = c.take(cells * 4);
       lv.t32 = c.take(cells * 4);
+      lv.rt32 = l == 0 ? c.take(cells * 4) : kAbsent;
     } else {
       lv.bx32 = lv.by32 = lv.bz32 = lv.f32 = lv.e32 = lv.t32 = kAbsent;
     }

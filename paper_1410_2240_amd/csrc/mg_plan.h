@@ -31,6 +31,7 @@ struct LevelPlan {
   size_t f = 0, e = 0;             // right-hand side / correction (levels >= 1)
   size_t t = 0;                    // second buffer for out-of-place sweeps
   size_t rt = kAbsent;             // level 0 only: rho on active cells, +inf elsewhere
+  size_t rt32 = kAbsent;           // level 0, mixed only: the same in FP32
   // FP32 arrays (mixed precision only)
   size_t bx32 = 0, by32 = 0, bz32 = 0;
   size_t f32 = 0, e32 = 0, t32 = 0;

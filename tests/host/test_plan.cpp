@@ -52,6 +52,8 @@ static void check_layout(int n, int flags) {
     }
     if (flags & 1) {
       for (size_t o : {a.bx32, a.by32, a.bz32, a.f32, a.e32, a.t32}) spans.push_back({o, c * 4});
+      if (l == 0) spans.push_back({a.rt32, c * 4});
+      else CHECK(a.rt32 == mg::kAbsent);
     } else {
       CHECK(a.bx32 == mg::kAbsent && a.f32 == mg::kAbsent);
     }

@@ -18,7 +18,7 @@ import torch
 import fields
 from oracle import multigrid as omg
 from oracle.operator import face_coeffs_from_rho, project
-from tests.gpu_helpers import dev, host, maxrel
+from tests.gpu_helpers import dev, host, maxrel, relerr
 
 pytestmark = pytest.mark.gpu
 
@@ -74,15 +74,48 @@ def test_solve_bitwise(mgpair):
     assert torch.equal(pa, pb)
 
 
-@pytest.mark.parametrize("mixed", [False, True])
-def test_fcg_and_mixed_bitwise(mixed):
-    inp, a, b = pair(128, mixed=mixed, krylov=True)
-    print(f"density-form FCG mixed={mixed}", flush=True)
+def test_fcg_bitwise():
+    inp, a, b = pair(128, krylov=True)
+    print("density-form FCG", flush=True)
     f = dev(inp.f)
     pa, ha, _ = a.solve(f, tol=1e-10, max_cycles=40)
     pb, hb, _ = b.solve(f, tol=1e-10, max_cycles=40)
     assert ha == hb
     assert torch.equal(pa, pb)
+
+
+@pytest.mark.parametrize("krylov", [False, True])
+def test_mixed_density_form_converges_to_the_same_solution(krylov):
+    """FP32 cycles form their finest coefficients from an FP32 density copy (not bitwise
+    the rounded FP64 faces); the FP64 refinement still reaches the same solution."""
+    inp, a, b = pair(128, mixed=True, krylov=krylov)
+    print(f"density-form mixed krylov={krylov}", flush=True)
+    f = dev(inp.f)
+    pa, ha, sa = a.solve(f, tol=1e-12, max_cycles=200)
+    pb, hb, sb = b.solve(f, tol=1e-12, max_cycles=200)
+    assert ha[-1] <= 1e-12 and hb[-1] <= 1e-12
+    assert abs(len(ha) - len(hb)) <= 2
+    assert relerr(host(pa), host(pb)) <= 1e-9
+
+
+@pytest.mark.parametrize("N", [64, 128])
+@pytest.mark.parametrize("order", [0, 1])
+def test_fp32_density_sweep_matches_emulation(N, order):
+    """The FP32 density-form sweep against the oracle's float32 Gauss-Seidel on the
+    operator formed from the density in single precision."""
+    inp = fields.make("c5", N)
+    from paper_1410_2240_amd import MG
+    mg = MG.from_rho(dev(inp.rho), dev(inp.mask), mixed=True)
+    H = omg.setup(*face_coeffs_from_rho(inp.rho, inp.mask), inp.mask, inp.h)
+    lev32 = omg.fp32_density_level(inp.rho, H.levels[0])
+    g = np.random.default_rng(21)
+    p = np.where(lev32.mask, g.standard_normal(lev32.bx.shape), 0.0).astype(np.float32)
+    f = project(g.standard_normal(lev32.bx.shape), lev32.mask).astype(np.float32)
+    want = omg.smooth(p, f, lev32, 2, (omg.RED, omg.BLACK) if order == 0 else (omg.BLACK, omg.RED))
+    got = host(mg.smooth(0, dev(p), dev(f), 2, order))
+    assert maxrel(got, want) <= 2e-5
+    rc = host(mg.residual_restrict(0, dev(p), dev(f)))
+    assert maxrel(rc, omg.restrict(omg.residual(p, f, lev32))) <= 2e-5
 
 
 @pytest.mark.parametrize("order", [0, 1])

@@ -329,3 +329,22 @@ def test_density_coarsening_smooths_a_sharp_interface():
     # coarse K = 0 holds fine planes k = 0 (water) and k = 1 (air)
     assert Hf.levels[1].bx[0, 0, 0] == pytest.approx(0.5 * (1.0 + 1e3))
     assert Hd.levels[1].bx[0, 0, 0] == pytest.approx(1.0 / (0.5 * (1.0 + 1e-3)))
+
+
+def test_fp32_density_level_is_the_rounded_operator_within_float_ulps():
+    """The single-precision operator formed from the density: within 2 float32 ulps of
+    round-to-nearest of the FP64 coefficients on open faces, exactly 0 on every face the
+    FP64 setup closes (body, dropped cells, bottom wall)."""
+    import fields
+    from oracle.multigrid import fp32_density_level, setup
+    from oracle.operator import face_coeffs_from_rho
+    inp = fields.make("c2", 32)
+    H = setup(*face_coeffs_from_rho(inp.rho, inp.mask), inp.mask, inp.h)
+    lev = H.levels[0]
+    l32 = fp32_density_level(inp.rho, lev)
+    for b32, b64 in ((l32.bx, lev.bx), (l32.by, lev.by), (l32.bz, lev.bz)):
+        assert b32.dtype == np.float32
+        assert np.array_equal(b32 == 0, b64 == 0)
+        ref = b64.astype(np.float32)
+        ulp = np.spacing(np.maximum(ref, np.float32(1e-30)))
+        assert np.max(np.abs(b32.astype(np.float64) - ref) / ulp) <= 2.0
