@@ -259,12 +259,15 @@ __global__ __launch_bounds__(TX / 2 * TY) void k_rbgs_fused(const T* __restrict_
   const int second = 1 - first;
   const T fs = fshift ? static_cast<T>(*fshift) : T(0);
   // A step branches on the colour parity of the thread's row, and contains barriers:
-  // every wave must hold rows of one parity.  With 32 pairs per row a wave spans two
-  // rows, so rows are paired as (0,2), (1,3), (4,6), (5,7).
+  // every wave must hold rows of one parity.  A wave spans R = 64 / (TX/2) rows (R = 1
+  // for TX >= 128); in each group of 2R tile rows one wave takes the even rows and the
+  // next wave the odd ones (TX = 64: (0,2), (1,3), (4,6), (5,7); TX = 32: (0,2,4,6),
+  // (1,3,5,7)).
+  constexpr int R = TX >= 128 ? 1 : 128 / TX;
+  static_assert(TY % (2 * R) == 0, "tile rows must split into waves of one parity");
   const int xt = tid % (TX / 2);
   const int half = tid / (TX / 2);
-  const int jt = TX >= 128 ? half : ((half & ~3) | ((half & 1) << 1) | ((half >> 1) & 1));
-  static_assert(TX >= 64, "a wave must not span rows of both parities");
+  const int jt = ((half / R) / 2) * (2 * R) + 2 * (half % R) + (half / R) % 2;
   const int jrow = j0 + jt;
   const int ipair = i0 + 2 * xt;
   const PairOffsets po{off_of<T>(ipair, jrow, q), off_of<T>(ipair - 1, jrow, q), off_of<T>(ipair + 2, jrow, q),
@@ -387,8 +390,8 @@ __global__ __launch_bounds__(TX / 2 * TY) void k_rbgs_fused(const T* __restrict_
   }
 
   // One step, for the first colour on plane k+1 sitting in the odd (ODD1) or even cell
-  // of the pair; a wave covers part of one tile row, so the choice is uniform per wave
-  // whenever a row holds at least 64 pairs.  On entry: plane k (first colour done on
+  // of the pair; a wave holds rows of one parity, so the choice is uniform per wave.
+  // On entry: plane k (first colour done on
   // tile + ring) in slot k, plane k+1 (old) in slot k+1, pn = plane k+2, raw = the
   // coefficients of plane k+1, black_cur = the second colour's on plane k.  One barrier
   // per step (after staging plane k+2): four slots let the next step stage its plane
@@ -486,6 +489,7 @@ hipError_t launch_tx(const T* pin, T* pout, const T* f, const T* bx, const T* by
 
 }  // namespace
 
+// (a 32^3 grid is faster with two half-sweeps: the one-pass sweep's prologue dominates)
 int fused_sweep_supported(int q) { return (1 << q) >= 64; }
 
 template <typename T>
