@@ -120,16 +120,19 @@ long long cells(const Level& a) { return static_cast<long long>(a.n) * a.n * a.n
 
 // `sweeps` red-black sweeps of A p = f on level l.  Large grids use the one-pass fused
 // sweep, which alternates p with the level's second buffer; an odd count ends with a
-// copy back.  Small grids use two in-place half-sweeps per sweep.
+// copy back.  Small grids use two in-place half-sweeps per sweep.  zero_in: p is known to
+// be zero, so the first one-pass sweep does not read it (p's memory may then hold
+// anything; half-sweep grids still need it zeroed).
 template <typename T>
-int smooth(mg_ctx* c, int l, T* p, const T* f, const double* fshift, int sweeps, int order) {
+int smooth(mg_ctx* c, int l, T* p, const T* f, const double* fshift, int sweeps, int order, bool zero_in = false) {
   const Level& a = c->lv[l];
   const View<T> v = c->view<T>(l);
   if (mg::fused_sweep_supported(a.q)) {
     T* src = p;
     T* dst = v.t;
     for (int s = 0; s < sweeps; ++s) {
-      MG_HIP(mg::launch_rbgs_fused<T>(src, dst, f, v.bx, v.by, v.bz, v.rt, a.q, a.h, order, fshift, c->stream));
+      MG_HIP(mg::launch_rbgs_fused<T>(src, dst, f, v.bx, v.by, v.bz, v.rt, a.q, a.h, order, fshift,
+                                      zero_in && s == 0, c->stream));
       T* tmp = src;
       src = dst;
       dst = tmp;
@@ -160,8 +163,9 @@ int residual_restrict(mg_ctx* c, int l, const T* p, const T* f, const double* fs
   return MG_OK;
 }
 
+// zero_in: p enters as zero (a correction), see smooth()
 template <typename T>
-int vcycle(mg_ctx* c, int l, T* p, const T* f, const double* fshift) {
+int vcycle(mg_ctx* c, int l, T* p, const T* f, const double* fshift, bool zero_in = false) {
   if (c->lv[l].n <= mg::kCoarseCycleMaxN) {
     // grids of 16^3 and below: the rest of the cycle in one single-workgroup launch
     mg::CoarseCycle<T> a{};
@@ -185,9 +189,9 @@ int vcycle(mg_ctx* c, int l, T* p, const T* f, const double* fshift) {
     return MG_OK;
   }
   const View<T> next = c->view<T>(l + 1);
-  MG_TRY(smooth<T>(c, l, p, f, fshift, 2, MG_PRE));
+  MG_TRY(smooth<T>(c, l, p, f, fshift, 2, MG_PRE, zero_in));
   MG_TRY(residual_restrict<T>(c, l, p, f, fshift, next.f, next.e));
-  MG_TRY(vcycle<T>(c, l + 1, next.e, next.f, nullptr));
+  MG_TRY(vcycle<T>(c, l + 1, next.e, next.f, nullptr, true));   // restriction zeroed next.e
   MG_HIP(mg::launch_prolong_add<T>(next.e, p, c->lv[l].mask, c->lv[l].q, c->stream));
   MG_TRY(smooth<T>(c, l, p, f, fshift, 2, MG_POST));
   return MG_OK;
@@ -252,7 +256,11 @@ int solve_one(mg_ctx* c, const double* f, double* p, double tol, int max_cycles,
   // the residual pass also leaves the FP32 copy of r that the next FP32 cycle solves for
   float* r32 = mixed ? a.f32 : nullptr;
   float* e32 = mixed ? a.e32 : nullptr;
-  MG_TRY(residual_norm(c, p, f, fshift, r32, e32));
+  // corrections enter their cycle as zero; a one-pass-swept finest grid does not read
+  // them, so the passes before the cycle need not clear them
+  const bool zin = mg::fused_sweep_supported(a.q);
+  float* e32_zero = zin ? nullptr : e32;
+  MG_TRY(residual_norm(c, p, f, fshift, r32, e32_zero));
   double s[3];
   MG_TRY(read_scalars(c, s, 3));
   *removed_mean = s[S_FMEAN];
@@ -278,12 +286,13 @@ int solve_one(mg_ctx* c, const double* f, double* p, double tol, int max_cycles,
     const float* z32 = mixed ? e32 : nullptr;
     const double* z64 = mixed ? nullptr : kz;
     auto precondition = [&]() -> int {
-      if (mixed) return vcycle<float>(c, 0, e32, r32, nullptr);
-      return vcycle<double>(c, 0, kz, kr, nullptr);
+      if (mixed) return vcycle<float>(c, 0, e32, r32, nullptr, true);
+      return vcycle<double>(c, 0, kz, kr, nullptr, true);
     };
+    double* kz_zero = (mixed || zin) ? nullptr : kz;
     if (std::isfinite(r) && r > tol && max_cycles > 0) {
       // the first residual pass also wrote r (and zeroed the preconditioner output)
-      MG_TRY(residual_norm(c, p, f, fshift, r32, e32, kr, mixed ? nullptr : kz));
+      MG_TRY(residual_norm(c, p, f, fshift, r32, e32_zero, kr, kz_zero));
       MG_TRY(precondition());
       MG_HIP(mg::launch_fcg_dir(z64, z32, kd, nullptr, nullptr, q, c->stream));
     }
@@ -297,8 +306,8 @@ int solve_one(mg_ctx* c, const double* f, double* p, double tol, int max_cycles,
                                  c->stream));
       MG_TRY(reduce_set(c, 0, nb, S_DW));
       MG_TRY(reduce_set(c, 1, nb, S_DR));
-      MG_HIP(mg::launch_fcg_update(p, kr, kd, kw, c->scal + S_DR, c->scal + S_DW, q, mixed ? nullptr : kz,
-                                   mixed ? r32 : nullptr, mixed ? e32 : nullptr, part(c, 2), &nb, c->stream));
+      MG_HIP(mg::launch_fcg_update(p, kr, kd, kw, c->scal + S_DR, c->scal + S_DW, q, kz_zero,
+                                   mixed ? r32 : nullptr, mixed ? e32_zero : nullptr, part(c, 2), &nb, c->stream));
       MG_TRY(reduce_set(c, 2, nb, S_RNORM2));
       ++*cycles;
       double sn[8];
@@ -321,13 +330,13 @@ int solve_one(mg_ctx* c, const double* f, double* p, double tol, int max_cycles,
   while (!(c->flags & MG_KRYLOV) && std::isfinite(r) && r > tol && *cycles < max_cycles) {
     if (mixed) {
       // FP32 V-cycle for the correction from the FP32 copy of the FP64 residual, FP64 update
-      MG_TRY(vcycle<float>(c, 0, e32, r32, nullptr));
+      MG_TRY(vcycle<float>(c, 0, e32, r32, nullptr, true));
       MG_HIP(mg::launch_update_p(p, e32, a.mask, a.q, c->stream));
     } else {
       MG_TRY(vcycle<double>(c, 0, p, f, fshift));
     }
     ++*cycles;
-    MG_TRY(residual_norm(c, p, f, fshift, r32, e32));
+    MG_TRY(residual_norm(c, p, f, fshift, r32, e32_zero));
     double sn[3];
     MG_TRY(read_scalars(c, sn, 3));
     r = std::sqrt(sn[S_RNORM2]) / nf;

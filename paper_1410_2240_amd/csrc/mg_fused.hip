@@ -231,7 +231,7 @@ __device__ __forceinline__ void gs(T (*cur)[2][W / 2], int r, int c, T lo, T hi,
 // Tiles of TX x TY cells, one thread per x-pair of tile cells: 64 x 8 and 128 x 8 for
 // N = 64 and 128 (the x halo wraps onto the tile's own cache lines), 128 x 16 above
 // (one wave per tile row; fewer halo rows and ring cells per tile cell than 256 x 8).
-template <typename T, int TX, int TY, bool RHO>
+template <typename T, int TX, int TY, bool RHO, bool ZIN>
 __global__ __launch_bounds__(TX / 2 * TY) void k_rbgs_fused(const T* __restrict__ pin, T* __restrict__ pout,
                                                               const T* __restrict__ f, const T* __restrict__ bx,
                                                               const T* __restrict__ by, const T* __restrict__ bz,
@@ -283,9 +283,14 @@ __global__ __launch_bounds__(TX / 2 * TY) void k_rbgs_fused(const T* __restrict_
     op[u] = e < BOX ? off_of<T>(i0 - 2 + 2 * cp, j0 - 2 + r, q) : 0u;   // past the box: a harmless load
   }
   auto fetch_plane = [&](int kk) {   // a plane outside the grid reads as 0
-    const Rsrc pk = plane_rsrc(pin, kk, q);
+    if constexpr (ZIN) {   // the input is known to be zero: nothing to read
 #pragma unroll
-    for (int u = 0; u < PER; ++u) pn[u] = ld2(pk, op[u], T());
+      for (int u = 0; u < PER; ++u) pn[u] = V2{T(0), T(0)};
+    } else {
+      const Rsrc pk = plane_rsrc(pin, kk, q);
+#pragma unroll
+      for (int u = 0; u < PER; ++u) pn[u] = ld2(pk, op[u], T());
+    }
   };
   auto store_plane = [&](int slot) {
 #pragma unroll
@@ -350,7 +355,7 @@ __global__ __launch_bounds__(TX / 2 * TY) void k_rbgs_fused(const T* __restrict_
       ring_0 = coef_at(ri_, rj_, k0);
     }
     T pm2_0 = T(0), pm2_1 = T(0);   // the pair on plane k0-2
-    {
+    if constexpr (!ZIN) {
       const V2 v = ld2(plane_rsrc(pin, k0 - 2, q), po.c, T());   // 0 below the grid
       pm2_0 = v.x;
       pm2_1 = v.y;
@@ -460,7 +465,7 @@ __global__ __launch_bounds__(TX / 2 * TY) void k_rbgs_fused(const T* __restrict_
   }
 }
 
-template <typename T, int TX, int TY>
+template <typename T, int TX, int TY, bool ZIN>
 hipError_t launch_tx(const T* pin, T* pout, const T* f, const T* bx, const T* by, const T* bz, const T* rt, int q,
                      double h, int order, const double* fshift, hipStream_t s) {
   const int n = 1 << q;
@@ -478,11 +483,11 @@ hipError_t launch_tx(const T* pin, T* pout, const T* f, const T* bx, const T* by
   const int first = order == 0 ? 0 : 1;   // pre-smoothing: red first; post-smoothing: black first
   const dim3 grid(static_cast<unsigned>(blocks));
   if (rt) {
-    hipLaunchKernelGGL((k_rbgs_fused<T, TX, TY, true>), grid, dim3(threads), 0, s, pin, pout, f, bx, by, bz, rt, q, kc,
+    hipLaunchKernelGGL((k_rbgs_fused<T, TX, TY, true, ZIN>), grid, dim3(threads), 0, s, pin, pout, f, bx, by, bz, rt, q, kc,
                        h2, first, fshift);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL((k_rbgs_fused<T, TX, TY, false>), grid, dim3(threads), 0, s, pin, pout, f, bx, by, bz, rt, q, kc, h2,
+  hipLaunchKernelGGL((k_rbgs_fused<T, TX, TY, false, ZIN>), grid, dim3(threads), 0, s, pin, pout, f, bx, by, bz, rt, q, kc, h2,
                      first, fshift);
   return hipGetLastError();
 }
@@ -492,20 +497,28 @@ hipError_t launch_tx(const T* pin, T* pout, const T* f, const T* bx, const T* by
 // (a 32^3 grid is faster with two half-sweeps: the one-pass sweep's prologue dominates)
 int fused_sweep_supported(int q) { return (1 << q) >= 64; }
 
+template <typename T, bool ZIN>
+hipError_t launch_shape(const T* pin, T* pout, const T* f, const T* bx, const T* by, const T* bz, const T* rt, int q,
+                        double h, int order, const double* fshift, hipStream_t s) {
+  const int n = 1 << q;
+  if (n == 64) return launch_tx<T, 64, 8, ZIN>(pin, pout, f, bx, by, bz, rt, q, h, order, fshift, s);
+  if (n == 128) return launch_tx<T, 128, 8, ZIN>(pin, pout, f, bx, by, bz, rt, q, h, order, fshift, s);
+  return launch_tx<T, 128, 16, ZIN>(pin, pout, f, bx, by, bz, rt, q, h, order, fshift, s);
+}
+
 template <typename T>
 hipError_t launch_rbgs_fused(const T* pin, T* pout, const T* f, const T* bx, const T* by, const T* bz, const T* rt,
-                             int q, double h, int order, const double* fshift, hipStream_t s) {
-  const int n = 1 << q;
-  if (n < 64) return hipErrorInvalidValue;
-  if (n == 64) return launch_tx<T, 64, 8>(pin, pout, f, bx, by, bz, rt, q, h, order, fshift, s);
-  if (n == 128) return launch_tx<T, 128, 8>(pin, pout, f, bx, by, bz, rt, q, h, order, fshift, s);
-  return launch_tx<T, 128, 16>(pin, pout, f, bx, by, bz, rt, q, h, order, fshift, s);
+                             int q, double h, int order, const double* fshift, int zero_in, hipStream_t s) {
+  if ((1 << q) < 64) return hipErrorInvalidValue;
+  return zero_in ? launch_shape<T, true>(pin, pout, f, bx, by, bz, rt, q, h, order, fshift, s)
+                 : launch_shape<T, false>(pin, pout, f, bx, by, bz, rt, q, h, order, fshift, s);
 }
 
 template hipError_t launch_rbgs_fused<double>(const double*, double*, const double*, const double*, const double*,
-                                              const double*, const double*, int, double, int, const double*,
+                                              const double*, const double*, int, double, int, const double*, int,
                                               hipStream_t);
 template hipError_t launch_rbgs_fused<float>(const float*, float*, const float*, const float*, const float*,
-                                             const float*, const float*, int, double, int, const double*, hipStream_t);
+                                             const float*, const float*, int, double, int, const double*, int,
+                                             hipStream_t);
 
 }  // namespace mg

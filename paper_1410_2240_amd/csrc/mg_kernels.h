@@ -80,11 +80,12 @@ hipError_t launch_rbgs_half(T* p, const T* f, const T* bx, const T* by, const T*
                             double h, int colour, const double* fshift, hipStream_t s);
 // One full red-black sweep in one pass, out of place (pin -> pout, distinct buffers);
 // order 0 = red then black, 1 = black then red.  Grids with at least 64 cells per side.
-// rt != nullptr (FP64 only): coefficients from the density form instead of bx, by, bz.
+// rt != nullptr: coefficients from the density form instead of bx, by, bz.  zero_in:
+// the input is known to be zero (a correction's first sweep), so pin is not read.
 int fused_sweep_supported(int q);
 template <typename T>
 hipError_t launch_rbgs_fused(const T* pin, T* pout, const T* f, const T* bx, const T* by, const T* bz, const T* rt,
-                             int q, double h, int order, const double* fshift, hipStream_t s);
+                             int q, double h, int order, const double* fshift, int zero_in, hipStream_t s);
 template <typename T>
 hipError_t launch_residual_restrict(const T* p, const T* f, const T* bx, const T* by, const T* bz, const T* rt,
                                     int q, double h, const double* fshift, T* fc, T* ec_zero,
@@ -134,7 +135,7 @@ hipError_t launch_fcg_aw_march(const double* d, const double* r, const double* b
 // ---- FP64 finest-grid passes ------------------------------------------------------
 // partials[blockIdx] = sum over active cells of r^2, r = (f - fshift) - A p; optional
 // r32 = float(r) and e32 = 0 (mixed-precision refinement); returns the block count used.
-// optional outputs: r32 = float(r) with e32 = 0; r64 = r with z64 = 0 (flexible CG)
+// optional outputs (each may be null): r32 = float(r), e32 = 0, r64 = r, z64 = 0
 hipError_t launch_residual_norm(const double* p, const double* f, const double* bx, const double* by,
                                 const double* bz, const double* rt, int q, double h, const double* fshift,
                                 float* r32, float* e32_zero, double* r64, double* z64, double* partials,

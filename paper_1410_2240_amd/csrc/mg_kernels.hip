@@ -638,10 +638,8 @@ __global__ __launch_bounds__(kBlock) void k_residual_norm(const double* __restri
     pair_residual<double, RHO>(p, f, K, i, j, k, q, inv_h2, fs, r0, r1);
     acc = fmad(r1, r1, fmad(r0, r0, acc));
     const int c = cell(i, j, k, q);
-    if (r32) {
-      *reinterpret_cast<float2*>(r32 + c) = float2{static_cast<float>(r0), static_cast<float>(r1)};
-      *reinterpret_cast<float2*>(e32 + c) = float2{0.0f, 0.0f};
-    }
+    if (r32) *reinterpret_cast<float2*>(r32 + c) = float2{static_cast<float>(r0), static_cast<float>(r1)};
+    if (e32) *reinterpret_cast<float2*>(e32 + c) = float2{0.0f, 0.0f};
     if (r64) *reinterpret_cast<double2*>(r64 + c) = double2{r0, r1};
     if (z64) *reinterpret_cast<double2*>(z64 + c) = double2{0.0, 0.0};
   }
@@ -800,12 +798,9 @@ __global__ __launch_bounds__(kBlock) void k_fcg_update(double* __restrict__ p, d
     *reinterpret_cast<double2*>(p + c) = pv;
     *reinterpret_cast<double2*>(r + c) = rv;
     rr += rv.x * rv.x + rv.y * rv.y;
-    if (r32) {
-      *reinterpret_cast<float2*>(r32 + c) = float2{static_cast<float>(rv.x), static_cast<float>(rv.y)};
-      *reinterpret_cast<float2*>(e32_zero + c) = float2{0.0f, 0.0f};
-    } else {
-      *reinterpret_cast<double2*>(z_zero + c) = double2{0.0, 0.0};
-    }
+    if (r32) *reinterpret_cast<float2*>(r32 + c) = float2{static_cast<float>(rv.x), static_cast<float>(rv.y)};
+    if (e32_zero) *reinterpret_cast<float2*>(e32_zero + c) = float2{0.0f, 0.0f};
+    if (z_zero) *reinterpret_cast<double2*>(z_zero + c) = double2{0.0, 0.0};
   }
   const double s = block_sum(rr);
   if (threadIdx.x == 0) part_rr[blockIdx.x] = s;

@@ -8,8 +8,8 @@
 // rows just below and above the thread's two rows and the x neighbours come from the
 // caches (neighbouring threads load them as their own).  All loads address one plane
 // through a buffer descriptor (mg_buffer.h).  Modes:
-//   NORM      partial sums of r^2 per workgroup; optionally r32 = float(r) with
-//             e32 = 0, or r64 = r with z64 = 0
+//   NORM      partial sums of r^2 per workgroup; optionally r32 = float(r), e32 = 0,
+//             r64 = r, z64 = 0 (each output may be null)
 //   RESTRICT  fc = mean of r over the 8 children of each coarse cell (the pair's two
 //             cells on two rows and two planes), ec = 0
 //   AW        w = A d (flexible CG) with partial sums of d.w and d.r
@@ -205,6 +205,8 @@ __global__ __launch_bounds__(kMarchThreads) void k_residual_march(MarchArgs a) {
       if (a.r32) {
         *reinterpret_cast<float2*>(a.r32 + ca) = float2{static_cast<float>(r0a), static_cast<float>(r1a)};
         *reinterpret_cast<float2*>(a.r32 + cb) = float2{static_cast<float>(r0b), static_cast<float>(r1b)};
+      }
+      if (a.e32) {
         *reinterpret_cast<float2*>(a.e32 + ca) = float2{0.0f, 0.0f};
         *reinterpret_cast<float2*>(a.e32 + cb) = float2{0.0f, 0.0f};
       }
