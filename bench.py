@@ -251,7 +251,7 @@ def recorded_traffic(workload, N):
     workload or the kernel source has changed since."""
     import hashlib
     try:
-        rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))["k_rbgs_fused<double, 128, 16, true>"]
+        rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))["k_rbgs_fused<double, 128, 16, true, false>"]
     except (OSError, KeyError, ValueError):
         return None
     src = open(os.path.join(ROOT, rec["source"]), "rb").read()
