@@ -100,6 +100,7 @@ class MG:
                                        _ptr(mask, torch.uint8), _lib.dims3(n), self.h, flags, _stream(ref.device))
         _check(rc, "mg_setup")
         self._ctx = ctx
+        self._destroy = lib.mg_destroy   # kept so that teardown at interpreter exit still finds it
         self.levels = lib.mg_level_info(ctx, 0, None, None)
 
     @classmethod
@@ -113,8 +114,9 @@ class MG:
 
     def __del__(self):
         ctx = getattr(self, "_ctx", None)
-        if ctx is not None and ctx.value:
-            _lib.load().mg_destroy(ctx)
+        destroy = getattr(self, "_destroy", None)
+        if ctx is not None and ctx.value and destroy is not None:
+            destroy(ctx)
             self._ctx = None
 
     def _sync_stream(self):
