@@ -51,3 +51,27 @@ def test_workspace_size_is_host_arithmetic():
     assert lib.mg_workspace_size((ctypes.c_int * 3)(64, 64, 32), 0) == 0
     assert lib.mg_workspace_size(_lib.dims3(64), 8) == 0
     assert lib.mg_workspace_size(_lib.dims3(64), 4) == lib.mg_workspace_size(_lib.dims3(64), 0)
+
+
+def test_invalid_arguments_rejected_on_the_host():
+    """Argument checks run on the host before any device work: bad dims, null arrays and
+    unsupported sample counts return MG_EINVAL with a message (no GPU needed)."""
+    from paper_1410_2240_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("library not built")
+    lib = _lib.load()
+    fake = ctypes.c_void_p(256)   # never dereferenced: every call below fails validation first
+    good, bad = _lib.dims3(32), _lib.dims3(48)
+    assert lib.mg_cut_cells(fake, bad, 8, fake, fake, fake, fake, fake, None) == _lib.MG_EINVAL
+    assert lib.mg_cut_cells(fake, good, 3, fake, fake, fake, fake, fake, None) == _lib.MG_EINVAL
+    assert "samples" in _lib.last_error()
+    assert lib.mg_cut_cells(None, good, 8, fake, fake, fake, fake, fake, None) == _lib.MG_EINVAL
+    assert lib.mg_cut_coeffs(fake, fake, fake, fake, fake, None, good, fake, fake, fake, fake, None) == _lib.MG_EINVAL
+    assert lib.mg_merge_rhs(fake, fake, fake, good, None) == _lib.MG_EINVAL   # f_merged aliases f
+    assert "alias" in _lib.last_error()
+    assert lib.mg_merge_fill(None, fake, good, None) == _lib.MG_EINVAL
+    assert lib.mg_coeffs_from_rho(fake, fake, bad, fake, fake, fake, None) == _lib.MG_EINVAL
+    ctx = ctypes.c_void_p()
+    assert lib.mg_setup_from_rho(ctypes.byref(ctx), fake, 1 << 20, fake, fake, good, 1.0 / 32, 8, None) == _lib.MG_EINVAL
+    assert lib.mg_setup_from_rho(ctypes.byref(ctx), fake, 16, fake, fake, good, 1.0 / 32, 0, None) == _lib.MG_EWORKSPACE
+    assert not ctx.value
