@@ -94,6 +94,25 @@ def test_flat_128_mixed_matches_fft():
         assert relerr(host(p), pe) <= 1e-9, mixed
 
 
+def test_flat_512_fp64_and_mixed_match_fft_exact():
+    """The 512^3 mixed-precision workload at its full size (1-cell smear, density ratio
+    1000): FP64 V-cycles and FP32 cycles inside FP64 refinement, both to 1e-12, against
+    the oracle's exact FFT + Thomas solution."""
+    import fields as F
+    from oracle.operator import Level, face_coeffs_from_rho
+    inp = F.make("c3", 512)
+    print("512^3 c3: oracle FFT solve", flush=True)
+    lev = Level(*face_coeffs_from_rho(inp.rho, inp.mask), inp.mask.astype(bool), inp.h)
+    pe = exact.solve_fft_z(lev, inp.f)
+    del lev
+    for mixed in (False, True):
+        print(f"512^3 c3: GPU solve mixed={mixed}", flush=True)
+        p, hist, st = mg_from_inputs(inp, mixed).solve(dev(inp.f), tol=1e-12, max_cycles=100)
+        assert relerr(host(p), pe) <= 1e-9, (mixed, hist[-1])
+        del p
+        torch.cuda.empty_cache()
+
+
 def test_bench_workload_256_residual_by_oracle():
     """The benchmarked 256^3 wavy-interface + body workload, solved as the benchmark
     does (FP64 and mixed, tol 1e-10): the oracle recomputes the residual in FP64."""
