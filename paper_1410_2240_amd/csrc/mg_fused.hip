@@ -133,36 +133,59 @@ struct PairRho {
   T l, r;                              // rt at i-1 and i+2
 };
 
-// Loads outside the grid are clamped onto plane 0 and their values replaced after the
-// load (no branch around a load, so the compiler keeps everything in registers).
+// A plane outside the grid reads as 0 through its buffer descriptor; its densities are
+// +inf (beyond a z wall).  The replacement is a separate step, applied where the values
+// are first used: done at the load, it would make the compiler wait for a prefetch in
+// the step that issues it instead of the step that consumes it.
+template <typename T>
+__device__ __forceinline__ typename Vec2<T>::type wall_rho(typename Vec2<T>::type v, int kk, int q) {
+  const T inf = __builtin_huge_val();
+  const bool in = kk >= 0 && kk < (1 << q);
+  return typename Vec2<T>::type{in ? v.x : inf, in ? v.y : inf};
+}
+
+template <typename T>
+__device__ __forceinline__ typename Vec2<T>::type load_centre_raw(const T* __restrict__ rt, unsigned oc, int kk,
+                                                                  int q) {
+  return ld2(plane_rsrc(rt, kk, q), oc, T());
+}
+
 template <typename T>
 __device__ __forceinline__ typename Vec2<T>::type load_centre(const T* __restrict__ rt, unsigned oc, int kk, int q) {
+  return wall_rho<T>(load_centre_raw(rt, oc, kk, q), kk, q);
+}
+
+// raw loads of a plane's f and in-plane densities (planes outside the grid read 0)
+template <typename T>
+__device__ __forceinline__ void load_pair_rho_raw(PairRho<T>& R, const T* __restrict__ f, const T* __restrict__ rt,
+                                                  typename Vec2<T>::type centre, const PairOffsets& o, int kk, int q) {
+  const Rsrc rk = plane_rsrc(rt, kk, q);
+  R.c = centre;
+  R.f = ld2(plane_rsrc(f, kk, q), o.c, T());
+  R.l = ld1(rk, o.xl, T());
+  R.r = ld1(rk, o.xr, T());
+  R.s = ld2(rk, o.yd, T());
+  R.n = ld2(rk, o.yu, T());
+}
+
+// the wall replacement of a plane's densities loaded by load_pair_rho_raw (the centre
+// included: replacing it twice is harmless)
+template <typename T>
+__device__ __forceinline__ void wall_pair_rho(PairRho<T>& R, int kk, int q) {
   using V2 = typename Vec2<T>::type;
-  const T inf = __builtin_huge_val();
-  const bool in = kk >= 0 && kk < (1 << q);   // beyond a z wall: +inf
-  const V2 v = ld2(plane_rsrc(rt, kk, q), oc, T());
-  return V2{in ? v.x : inf, in ? v.y : inf};
+  R.c = wall_rho<T>(R.c, kk, q);
+  const V2 lr = wall_rho<T>(V2{R.l, R.r}, kk, q);
+  R.l = lr.x;
+  R.r = lr.y;
+  R.s = wall_rho<T>(R.s, kk, q);
+  R.n = wall_rho<T>(R.n, kk, q);
 }
 
 template <typename T>
 __device__ __forceinline__ void load_pair_rho(PairRho<T>& R, const T* __restrict__ f, const T* __restrict__ rt,
                                               typename Vec2<T>::type centre, const PairOffsets& o, int kk, int q) {
-  using V2 = typename Vec2<T>::type;
-  const int n = 1 << q;
-  const T inf = __builtin_huge_val();
-  const bool in = kk >= 0 && kk < n;
-  const Rsrc rk = plane_rsrc(rt, kk, q);
-  const V2 fv = ld2(plane_rsrc(f, kk, q), o.c, T());   // 0 outside the grid
-  const T l = ld1(rk, o.xl, T());
-  const T r = ld1(rk, o.xr, T());
-  const V2 sv = ld2(rk, o.yd, T());
-  const V2 nv = ld2(rk, o.yu, T());
-  R.c = centre;
-  R.f = fv;
-  R.l = in ? l : inf;
-  R.r = in ? r : inf;
-  R.s = V2{in ? sv.x : inf, in ? sv.y : inf};
-  R.n = V2{in ? nv.x : inf, in ? nv.y : inf};
+  load_pair_rho_raw(R, f, rt, centre, o, kk, q);
+  wall_pair_rho(R, kk, q);
 }
 
 // Both cells' coefficients of a pair from its plane's densities, every face once: zm
@@ -200,6 +223,53 @@ __device__ __forceinline__ Coef<T> load_cell_rho(const T* __restrict__ f, const 
   C.yp = beta_rho(rc, ld1(rk, off_of<T>(i, j + 1, q), T()));
   C.zm = kk > 0 ? beta_rho(ld1(plane_rsrc(rt, kk - 1, q), oc, T()), rc) : T(0);
   C.zp = kk < n - 1 ? beta_rho(rc, ld1(plane_rsrc(rt, kk + 1, q), oc, T())) : T(0);
+  return C;
+}
+
+// A ring cell's f and densities as raw loads (its plane and the planes below and above
+// through their buffer descriptors, 0 outside the grid) ...
+template <typename T>
+struct CellRho {
+  T f, c, l, r, s, n, lo, hi;
+};
+
+template <typename T>
+__device__ __forceinline__ CellRho<T> load_cell_rho_raw(const T* __restrict__ f, const T* __restrict__ rt, int i,
+                                                        int j, int kk, int q) {
+  CellRho<T> R;
+  const unsigned oc = off_of<T>(i, j, q);
+  const Rsrc rk = plane_rsrc(rt, kk, q);
+  R.f = ld1(plane_rsrc(f, kk, q), oc, T());
+  R.c = ld1(rk, oc, T());
+  R.l = ld1(rk, off_of<T>(i - 1, j, q), T());
+  R.r = ld1(rk, off_of<T>(i + 1, j, q), T());
+  R.s = ld1(rk, off_of<T>(i, j - 1, q), T());
+  R.n = ld1(rk, off_of<T>(i, j + 1, q), T());
+  R.lo = ld1(plane_rsrc(rt, kk - 1, q), oc, T());
+  R.hi = ld1(plane_rsrc(rt, kk + 1, q), oc, T());
+  return R;
+}
+
+// ... and its coefficients once they are needed: densities beyond a z wall become +inf,
+// which closes those faces, so this equals load_cell_rho bit for bit (a plane outside
+// the grid gets f = 0 and six closed faces)
+template <typename T>
+__device__ __forceinline__ Coef<T> cell_coef_rho(const CellRho<T>& R, int kk, int q) {
+  using V2 = typename Vec2<T>::type;
+  const V2 cl = wall_rho<T>(V2{R.c, R.l}, kk, q);
+  const V2 rs = wall_rho<T>(V2{R.r, R.s}, kk, q);
+  const T nn = wall_rho<T>(V2{R.n, R.n}, kk, q).x;
+  const T lo = wall_rho<T>(V2{R.lo, R.lo}, kk - 1, q).x;
+  const T hi = wall_rho<T>(V2{R.hi, R.hi}, kk + 1, q).x;
+  const T c = cl.x;
+  Coef<T> C;
+  C.f = R.f;
+  C.xm = beta_rho(cl.y, c);
+  C.xp = beta_rho(c, rs.x);
+  C.ym = beta_rho(rs.y, c);
+  C.yp = beta_rho(c, nn);
+  C.zm = beta_rho(lo, c);
+  C.zp = beta_rho(c, hi);
   return C;
 }
 
@@ -244,6 +314,11 @@ __global__ __launch_bounds__(TX / 2 * TY) void k_rbgs_fused(const T* __restrict_
   constexpr int BOX = H * (W / 2);          // pairs per staged plane
   constexpr int PER = (BOX + NT - 1) / NT;  // pairs per thread
   __shared__ T L[4][H][2][W / 2];
+  // FP64: the second colour's coefficients, carried from one step to the next, wait in
+  // LDS (each thread its own column of words) rather than in 14 registers, which the
+  // prefetches of the next planes need
+  constexpr bool CARRY_LDS = sizeof(T) == 8;
+  __shared__ T CB[CARRY_LDS ? 7 : 1][CARRY_LDS ? NT : 1];
   const int n = 1 << q, m = n - 1;
   const int tid = threadIdx.x;
   // Consecutive logical tiles run on one XCD (blocks are dealt to the 8 XCDs in turn):
@@ -343,12 +418,31 @@ __global__ __launch_bounds__(TX / 2 * TY) void k_rbgs_fused(const T* __restrict_
   PairRho<T> rraw;       // density form: the same plane's f and in-plane densities
   V2 rc_hi;              // density form: the pair's densities two planes up
   V2 zlo;                // density form: the pair's faces between the current plane and the next
-  Coef<T> black_cur;     // second colour's coefficients on the current plane
+  Coef<T> black_cur;     // second colour's coefficients on the current plane (or in CB)
+  auto put_black = [&](const Coef<T>& C) {
+    if constexpr (CARRY_LDS) {
+      CB[0][tid] = C.f;
+      CB[1][tid] = C.xm;
+      CB[2][tid] = C.xp;
+      CB[3][tid] = C.ym;
+      CB[4][tid] = C.yp;
+      CB[5][tid] = C.zm;
+      CB[6][tid] = C.zp;
+    } else {
+      black_cur = C;
+    }
+  };
+  auto get_black = [&]() {
+    if constexpr (CARRY_LDS)
+      return Coef<T>{CB[0][tid], CB[1][tid], CB[2][tid], CB[3][tid], CB[4][tid], CB[5][tid], CB[6][tid]};
+    else
+      return black_cur;
+  };
   T below0, below1;      // the pair's finished values on the plane under the current one
   {
     const Coef<T> red_m1 = coef_at(ipair + first_odd(k0 - 1), jrow, k0 - 1);
     const Coef<T> red_0 = coef_at(ipair + first_odd(k0), jrow, k0);
-    black_cur = coef_at(ipair + !first_odd(k0), jrow, k0);
+    put_black(coef_at(ipair + !first_odd(k0), jrow, k0));
     Coef<T> ring_0;
     if (has_ring) {
       ring_cell(k0, rr_, rc_, ri_, rj_);
@@ -391,6 +485,11 @@ __global__ __launch_bounds__(TX / 2 * TY) void k_rbgs_fused(const T* __restrict_
       ring_cell(k0, rr_, rc_, ri_, rj_);
       gs<T, W>(L[s0], rr_, rc_, at<T, W>(L[sm], rr_, rc_), at<T, W>(L[s1], rr_, rc_), ring_0, h2, fs);
     }
+    // Enter the loop with no load in flight.  The compiler counts outstanding loads
+    // across the loop entry and the back edge together; a prefetch still pending from
+    // here would make it wait for every load, this step's prefetches included, at the
+    // first use of a staged plane in every step.
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
   }
 
@@ -404,21 +503,26 @@ __global__ __launch_bounds__(TX / 2 * TY) void k_rbgs_fused(const T* __restrict_
   auto step = [&](int k, auto odd_tag) {
     constexpr bool ODD1 = decltype(odd_tag)::value;
     const int s0 = slot(k), s1 = slot(k + 1), s2 = slot(k + 2);
-    // the ring cell's coefficients first: they are used right after the barrier, and
-    // waiting for them must not wait for the prefetches of the planes above
+    // the ring cell's loads first: they are used right after the barrier, and waiting
+    // for them must not wait for the prefetches of the planes above (the density form
+    // forms the ring cell's faces after the barrier for the same reason)
     Coef<T> ring_c;
+    CellRho<T> ring_raw;
     if (has_ring) {
       ring_cell(k + 1, rr_, rc_, ri_, rj_);
-      ring_c = coef_at(ri_, rj_, k + 1);
+      if constexpr (RHO)
+        ring_raw = load_cell_rho_raw(f, rt, ri_, rj_, k + 1, q);
+      else
+        ring_c = load_cell(f, bx, by, bz, ri_, rj_, k + 1, q);
     }
     store_plane(s2);                   // plane k+2
     fetch_plane(k + 3);
     PairRaw<T> raw_next;
     PairRho<T> rraw_next;
     V2 rc_next;
-    if constexpr (RHO) {
-      load_pair_rho(rraw_next, f, rt, rc_hi, po, k + 2, q);
-      rc_next = load_centre(rt, po.c, k + 3, q);
+    if constexpr (RHO) {   // the wall replacement waits for the next step
+      load_pair_rho_raw(rraw_next, f, rt, rc_hi, po, k + 2, q);
+      rc_next = load_centre_raw(rt, po.c, k + 3, q);
     } else {
       load_pair(raw_next, f, bx, by, bz, po, k + 2, q);
     }
@@ -427,6 +531,8 @@ __global__ __launch_bounds__(TX / 2 * TY) void k_rbgs_fused(const T* __restrict_
     Coef<T> red, black_next;
     if constexpr (RHO) {
       Coef<T> ev, od;
+      wall_pair_rho(rraw, k + 1, q);
+      rc_hi = wall_rho<T>(rc_hi, k + 2, q);
       zlo = pair_coef_rho(rraw, zlo, rc_hi, ev, od);
       red = ODD1 ? od : ev;
       black_next = ODD1 ? ev : od;
@@ -437,22 +543,25 @@ __global__ __launch_bounds__(TX / 2 * TY) void k_rbgs_fused(const T* __restrict_
     if (k + 1 < n) {                   // first colour on plane k+1, tile and ring
       const int c = ct + ODD1;
       gs<T, W>(L[s1], rt_, c, at<T, W>(L[s0], rt_, c), at<T, W>(L[s2], rt_, c), red, h2, fs);
-      if (has_ring) gs<T, W>(L[s1], rr_, rc_, at<T, W>(L[s0], rr_, rc_), at<T, W>(L[s2], rr_, rc_), ring_c, h2, fs);
+      if (has_ring) {
+        if constexpr (RHO) ring_c = cell_coef_rho(ring_raw, k + 1, q);
+        gs<T, W>(L[s1], rr_, rc_, at<T, W>(L[s0], rr_, rc_), at<T, W>(L[s2], rr_, rc_), ring_c, h2, fs);
+      }
     }
     // no barrier: the second colour on plane k reads the first colour on plane k+1 only
     // in its own column, which this thread has just updated
     {                                  // second colour on plane k (same column), plane out
       const int c = ct + ODD1;
-      gs<T, W>(L[s0], rt_, c, ODD1 ? below1 : below0, at<T, W>(L[s1], rt_, c), black_cur, h2, fs);
+      gs<T, W>(L[s0], rt_, c, ODD1 ? below1 : below0, at<T, W>(L[s1], rt_, c), get_black(), h2, fs);
       below0 = at<T, W>(L[s0], rt_, ct);
       below1 = at<T, W>(L[s0], rt_, ct + 1);
       *reinterpret_cast<V2*>(reinterpret_cast<char*>(pout + (static_cast<long long>(k) << (2 * q))) + po.c) =
           V2{below0, below1};
     }
-    black_cur = black_next;
+    put_black(black_next);
     if constexpr (RHO) {
-      rraw = rraw_next;
-      rc_hi = rc_next;
+      rraw = rraw_next;   // plane k+2, replaced at the start of the next step
+      rc_hi = rc_next;    // plane k+3
     } else {
       raw = raw_next;
     }
