@@ -566,11 +566,28 @@ __global__ __launch_bounds__(TX / 2 * TY) void k_rbgs_fused(const T* __restrict_
       raw = raw_next;
     }
   };
-  for (int k = k0; k < k1; ++k) {
-    if (first_odd(k + 1))
+  // The colour of a thread's first cell alternates from plane to plane and is uniform
+  // per wave.  FP32: two steps per iteration, in one of two loops chosen once (kc is
+  // even), so each loop body is straight-line code whose memory waits the compiler counts
+  // exactly.  FP64 keeps one step per iteration: two would exceed the register budget
+  // of 1024-thread workgroups and spill.
+  if constexpr (sizeof(T) == 8) {
+    for (int k = k0; k < k1; ++k) {
+      if (first_odd(k + 1))
+        step(k, std::true_type{});
+      else
+        step(k, std::false_type{});
+    }
+  } else if (first_odd(k0 + 1)) {
+    for (int k = k0; k < k1; k += 2) {
       step(k, std::true_type{});
-    else
+      step(k + 1, std::false_type{});
+    }
+  } else {
+    for (int k = k0; k < k1; k += 2) {
       step(k, std::false_type{});
+      step(k + 1, std::true_type{});
+    }
   }
 }
 
