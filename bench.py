@@ -22,11 +22,12 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # Algorithmic scalars moved per finest cell by one V(2,2) cycle.  A grid with the face
 # arrays: 4 sweeps x 6 (p, f, bx, by, bz read, p written) + residual-and-restrict 5.125
-# + prolongation 2.125 = 31.25, and each coarser grid 1/8 of the one above.  The FP64
-# finest grid of a hierarchy built from rho reads one density instead of three face
-# arrays: 4 x 4 + 3.125 + 2.125 = 21.25, plus 31.25 / 7 for the coarser grids.
-VCYCLE_SCALARS_F32 = 31.25 * 8 / 7
+# + prolongation 2.125 = 31.25, and each coarser grid 1/8 of the one above.  The finest
+# grid of a hierarchy built from rho reads one density instead of three face arrays, in
+# FP64 and in the FP32 cycle alike: 4 x 4 + 3.125 + 2.125 = 21.25, plus 31.25 / 7 for
+# the coarser grids.
 VCYCLE_SCALARS_F64 = 21.25 + 31.25 / 7
+VCYCLE_SCALARS_F32 = VCYCLE_SCALARS_F64
 
 
 def parse():
