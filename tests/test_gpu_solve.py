@@ -124,6 +124,38 @@ def test_bench_workload_256_residual_by_oracle():
         assert abs(rr - hist[-1]) <= 1e-3 * hist[-1] + 1e-14
 
 
+@pytest.mark.slow
+def test_crest_1024_full_size_fcg_residual_by_oracle():
+    """The 1024^3 Stokes-crest + body workload at its full size, as it is timed: flexible
+    CG with FP64 and with mixed-precision cycles, both to 1e-10.  The oracle recomputes
+    each solution's residual in FP64, slab by slab (no oracle solve fits at this size);
+    the mixed solution is compared with the GPU's own FP64 one."""
+    from paper_1410_2240_amd import MG
+    from tests.slab_residual import slab_relres
+    print("1024^3 c5: generating the inputs", flush=True)
+    inp = fields.make("c5", 1024)
+    rho, mask, f = dev(inp.rho), dev(inp.mask), dev(inp.f)
+    sols = {}
+    for mixed in (False, True):
+        print(f"1024^3 c5: GPU flexible CG mixed={mixed}", flush=True)
+        mg = MG.from_rho(rho, mask, mixed=mixed, krylov=True)
+        p, hist, st = mg.solve(f, tol=1e-10, max_cycles=200)
+        assert st["status"] == 0 and hist[-1] <= 1e-10, (mixed, st, hist[-3:])
+        del mg
+        ph = host(p)
+        del p
+        torch.cuda.empty_cache()
+        print(f"1024^3 c5: oracle residual mixed={mixed}", flush=True)
+        rr = slab_relres(inp.rho, inp.mask, inp.f, ph, inp.h)
+        print(f"1024^3 c5: mixed={mixed} steps={len(hist) - 1} gpu {hist[-1]:.3e} oracle {rr:.3e}", flush=True)
+        assert rr <= 1.05e-10, (mixed, rr, hist[-3:])
+        assert abs(rr - hist[-1]) <= 1e-3 * hist[-1] + 1e-14
+        sols[mixed] = ph
+    d = relerr(sols[True], sols[False])
+    print(f"1024^3 c5: mixed vs FP64 solution {d:.3e}", flush=True)
+    assert d <= 1e-9
+
+
 def test_repeatable_bitwise():
     inp, _ = workload("c2", 32)
     mg = mg_from_inputs(inp)

@@ -120,3 +120,23 @@ def test_projection_removes_active_mean():
     f = np.random.default_rng(11).standard_normal((4, 4, 4)) + 3.0
     pf = project(f, mask)
     assert abs(pf[mask].sum()) < 1e-12 and np.all(pf[~mask] == 0)
+
+
+def test_slab_residual_equals_whole_grid_residual():
+    """The slab-by-slab residual used at 1024^3 equals the whole-array one (64^3 crest
+    field with the body, a random p, slabs of 8 planes and a ragged last slab)."""
+    import fields
+    from oracle.multigrid import setup
+    from oracle.operator import face_coeffs_from_rho, project
+    from tests.slab_residual import slab_relres
+    N = 64
+    inp = fields.make("c5", N)
+    H = setup(*face_coeffs_from_rho(inp.rho, inp.mask), inp.mask, inp.h)
+    p = np.random.default_rng(9).standard_normal((N, N, N)) * 1e-3
+    p = np.where(H.fine.mask, p, 0.0)
+    fh = project(inp.f, H.fine.mask)
+    r = np.where(H.fine.mask, fh - apply(p, H.fine), 0.0)
+    want = float(np.linalg.norm(r) / np.linalg.norm(fh))
+    for slab in (8, 24):
+        got = slab_relres(inp.rho, inp.mask, inp.f, p, inp.h, slab=slab, workers=3)
+        assert abs(got - want) <= 1e-12 * want, (slab, got, want)
