@@ -70,7 +70,7 @@ struct Level {
 template <typename T>
 struct View {
   T *bx, *by, *bz, *f, *e, *t;
-  const T* rt;   // density form of the coefficients (FP64 finest grid only), else null
+  const T* rt;   // finest grid of a hierarchy built from rho: the density form, else null
 };
 
 }  // namespace
@@ -495,19 +495,25 @@ int setup_impl(mg_ctx** out, void* workspace, size_t ws_bytes, const double* bx,
   hip(hipMemsetAsync(c->counters, 0, 16 * sizeof(long long), s), "hipMemsetAsync(counters)");
   Level& f0 = c->lv[0];
   if (rho) {
-    // face products (or, for density coarsening, open-face areas) straight into the
-    // workspace, then validation and activity without rewriting them
-    hip(mg::launch_coeffs_from_rho(density ? nullptr : rho, mask, f0.q, f0.bx, f0.by, f0.bz, s), "coeffs_from_rho");
-    hip(mg::launch_setup_fine(f0.bx, f0.by, f0.bz, mask, f0.q, nullptr, nullptr, nullptr, f0.mask, c->counters, s),
-        "setup_fine");
+    // density form of the finest coefficients, read by the finest-grid passes in place
+    // of the three face arrays
+    f0.rt = at<double>(c->ws, plan.lv[0].rt);
+    if (density) {
+      // open-face areas into the workspace, then validation and activity without
+      // rewriting them, then the density form
+      hip(mg::launch_coeffs_from_rho(nullptr, mask, f0.q, f0.bx, f0.by, f0.bz, s), "coeffs_from_rho");
+      hip(mg::launch_setup_fine(f0.bx, f0.by, f0.bz, mask, f0.q, nullptr, nullptr, nullptr, f0.mask, c->counters, s),
+          "setup_fine");
+      hip(mg::launch_rho_tilde(rho, f0.mask, f0.q, f0.rt, s), "rho_tilde");
+    } else {
+      // face products, validation, activity and the density form in one pass
+      hip(mg::launch_setup_from_rho(rho, mask, f0.q, f0.bx, f0.by, f0.bz, f0.mask, f0.rt, c->counters, s),
+          "setup_from_rho");
+    }
   } else {
     hip(mg::launch_setup_fine(bx, by, bz, mask, f0.q, f0.bx, f0.by, f0.bz, f0.mask, c->counters, s), "setup_fine");
   }
   if (rho) {
-    // density form of the finest coefficients, read by the finest-grid passes in place
-    // of the three face arrays
-    f0.rt = at<double>(c->ws, plan.lv[0].rt);
-    hip(mg::launch_rho_tilde(rho, f0.mask, f0.q, f0.rt, s), "rho_tilde");
     if ((flags & MG_MIXED) && mg::fused_sweep_supported(f0.q)) {
       // the FP32 cycles form their finest faces from an FP32 copy (one-pass sweep grids,
       // so that smoother and residual use the same FP32 operator)
@@ -533,7 +539,8 @@ int setup_impl(mg_ctx** out, void* workspace, size_t ws_bytes, const double* bx,
     }
   }
   if (flags & MG_MIXED) {
-    for (int l = 0; l < c->L; ++l) {
+    // (a finest grid with an FP32 density copy never reads its FP32 face arrays)
+    for (int l = f0.rt32 ? 1 : 0; l < c->L; ++l) {
       const Level& a = c->lv[l];
       hip(mg::launch_to_f32(a.bx, a.bx32, cells(a), s), "to_f32");
       hip(mg::launch_to_f32(a.by, a.by32, cells(a), s), "to_f32");

@@ -54,6 +54,10 @@ hipError_t launch_area_to_beta(const double* rho, int q, double* bx, double* by,
 hipError_t launch_setup_fine(const double* ubx, const double* uby, const double* ubz,
                              const uint8_t* umask, int q, double* bx, double* by, double* bz,
                              uint8_t* mask, long long* counters, hipStream_t s);
+// the three above for a hierarchy built from rho, in one pass: face products, their
+// validation and the active cells (counters as launch_setup_fine), and rt
+hipError_t launch_setup_from_rho(const double* rho, const uint8_t* umask, int q, double* bx, double* by, double* bz,
+                                 uint8_t* mask, double* rt, long long* counters, hipStream_t s);
 hipError_t launch_coarsen(const double* bx, const double* by, const double* bz, const uint8_t* mask,
                           int qc, double* cbx, double* cby, double* cbz, uint8_t* cmask, hipStream_t s);
 hipError_t launch_to_f32(const double* src, float* dst, long long count, hipStream_t s);

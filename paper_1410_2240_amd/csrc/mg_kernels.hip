@@ -306,6 +306,60 @@ __global__ __launch_bounds__(kBlock) void k_setup_fine(const double* __restrict_
   }
 }
 
+// The finest grid of a hierarchy built from rho in one pass: the face products
+// beta = 2 / (rho_L + rho_R) on faces between fluid cells (0 elsewhere and on the
+// bottom wall), their validation, the active cells (fluid with an open face) and the
+// density form rt (rho on active cells, +inf elsewhere).  The same values as
+// k_coeffs_from_rho, then k_setup_fine and k_rho_tilde: each face, the low ones stored
+// and the high ones summed into the diagonal, is face_beta of the same two densities.
+__global__ __launch_bounds__(kBlock) void k_setup_from_rho(const double* __restrict__ rho,
+                                                           const uint8_t* __restrict__ umask, int q,
+                                                           double* __restrict__ bx, double* __restrict__ by,
+                                                           double* __restrict__ bz, uint8_t* __restrict__ mask,
+                                                           double* __restrict__ rt, long long* __restrict__ counters) {
+  const int n = 1 << q, m = n - 1;
+  const int total = 1 << (3 * q);
+  const int nn = 1 << (2 * q);
+  int bad = 0, active = 0, dropped = 0;
+  auto ok = [](double v) { return v >= 0.0 && v <= 1.7976931348623157e308; };
+  for (int c = blockIdx.x * kBlock + threadIdx.x; c < total; c += gridDim.x * kBlock) {
+    const int i = c & m, j = (c >> q) & m, k = c >> (2 * q);
+    const bool mc = umask[c] != 0;
+    const int cxm = cell((i - 1) & m, j, k, q), cxp = cell((i + 1) & m, j, k, q);
+    const int cym = cell(i, (j - 1) & m, k, q), cyp = cell(i, (j + 1) & m, k, q);
+    const double rc = rho[c];
+    const double xm = (mc && umask[cxm]) ? face_beta(rc, rho[cxm]) : 0.0;
+    const double ym = (mc && umask[cym]) ? face_beta(rc, rho[cym]) : 0.0;
+    const double zm = (k > 0 && mc && umask[c - nn]) ? face_beta(rc, rho[c - nn]) : 0.0;
+    const double xp = (mc && umask[cxp]) ? face_beta(rho[cxp], rc) : 0.0;
+    const double yp = (mc && umask[cyp]) ? face_beta(rho[cyp], rc) : 0.0;
+    const double zp = (k < m && mc && umask[c + nn]) ? face_beta(rho[c + nn], rc) : 0.0;
+    bad += !ok(xm) + !ok(ym) + !ok(zm);
+    bx[c] = xm;
+    by[c] = ym;
+    bz[c] = zm;
+    const bool act = mc && (xm + xp + ym + yp + zm + zp) > 0.0;
+    mask[c] = act ? 1 : 0;
+    rt[c] = act ? rc : __builtin_huge_val();
+    active += act;
+    dropped += mc && !act;
+  }
+  __shared__ int red[3][kBlock / 64];
+  int v[3] = {bad, active, dropped};
+  for (int x = 0; x < 3; ++x)
+    for (int off = 32; off > 0; off >>= 1) v[x] += __shfl_xor(v[x], off, 64);
+  if ((threadIdx.x & 63) == 0)
+    for (int x = 0; x < 3; ++x) red[x][threadIdx.x >> 6] = v[x];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int x = 0; x < 3; ++x) {
+      long long sum = 0;
+      for (int w = 0; w < kBlock / 64; ++w) sum += red[x][w];
+      if (sum) atomicAdd(reinterpret_cast<unsigned long long*>(&counters[x]), static_cast<unsigned long long>(sum));
+    }
+  }
+}
+
 // Coarse face = mean of the 4 fine faces it covers; coarse cell active if any child is
 // active and it keeps an open face.  One thread per coarse cell.
 __global__ __launch_bounds__(kBlock) void k_coarsen(const double* __restrict__ bx, const double* __restrict__ by,
@@ -920,6 +974,13 @@ hipError_t launch_setup_fine(const double* ubx, const double* uby, const double*
                              hipStream_t s) {
   hipLaunchKernelGGL(k_setup_fine, dim3(reduction_blocks(1LL << (3 * q))), dim3(kBlock), 0, s, ubx, uby, ubz, umask, q,
                      bx, by, bz, mask, counters);
+  return hipGetLastError();
+}
+
+hipError_t launch_setup_from_rho(const double* rho, const uint8_t* umask, int q, double* bx, double* by, double* bz,
+                                 uint8_t* mask, double* rt, long long* counters, hipStream_t s) {
+  hipLaunchKernelGGL(k_setup_from_rho, dim3(reduction_blocks(1LL << (3 * q))), dim3(kBlock), 0, s, rho, umask, q, bx,
+                     by, bz, mask, rt, counters);
   return hipGetLastError();
 }
 
