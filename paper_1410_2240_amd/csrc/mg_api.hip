@@ -153,11 +153,9 @@ template <typename T>
 int residual_restrict(mg_ctx* c, int l, const T* p, const T* f, const double* fshift, T* fc, T* ec) {
   const Level& a = c->lv[l];
   const View<T> v = c->view<T>(l);
-  if constexpr (std::is_same<T, double>::value) {
-    if (mg::march_supported(a.q)) {
-      MG_HIP(mg::launch_residual_restrict_march(p, f, v.bx, v.by, v.bz, v.rt, a.q, a.h, fshift, fc, ec, c->stream));
-      return MG_OK;
-    }
+  if (mg::march_supported(a.q)) {
+    MG_HIP(mg::launch_residual_restrict_march<T>(p, f, v.bx, v.by, v.bz, v.rt, a.q, a.h, fshift, fc, ec, c->stream));
+    return MG_OK;
   }
   MG_HIP(mg::launch_residual_restrict<T>(p, f, v.bx, v.by, v.bz, v.rt, a.q, a.h, fshift, fc, ec, c->stream));
   return MG_OK;

@@ -129,9 +129,10 @@ hipError_t launch_residual_norm_march(const double* p, const double* f, const do
                                       const double* bz, const double* rt, int q, double h, const double* fshift,
                                       float* r32, float* e32, double* r64, double* z64, double* partials,
                                       int* nblocks, hipStream_t s);
-hipError_t launch_residual_restrict_march(const double* p, const double* f, const double* bx, const double* by,
-                                          const double* bz, const double* rt, int q, double h, const double* fshift,
-                                          double* fc, double* ec, hipStream_t s);
+// (FP64 and FP32: the restriction is the one pass an FP32 cycle marches)
+template <typename T>
+hipError_t launch_residual_restrict_march(const T* p, const T* f, const T* bx, const T* by, const T* bz, const T* rt,
+                                          int q, double h, const double* fshift, T* fc, T* ec, hipStream_t s);
 hipError_t launch_fcg_aw_march(const double* d, const double* r, const double* bx, const double* by, const double* bz,
                                const double* rt, int q, double h, double* w, double* part_dw, double* part_dr,
                                int* nblocks, hipStream_t s);

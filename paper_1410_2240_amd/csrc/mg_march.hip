@@ -1,4 +1,4 @@
-// Finest-grid residual passes that march up z (CDNA4, FP64).
+// Residual passes that march up z (CDNA4; FP64, and FP32 for the restriction).
 //
 // r = (f - fshift) - h^-2 sum_f beta_f (p_nb - p_c) on active cells (D = sum beta > 0),
 // 0 elsewhere.  Each thread owns an x-pair (i even, i+1) in two rows (2J, 2J+1) of a
@@ -31,22 +31,26 @@ using buf::ld2;
 using buf::off_of;
 using buf::plane_rsrc;
 using buf::Rsrc;
+using buf::Vec2;
 
 constexpr int kMarchThreads = 256;
 enum { kModeNorm = 0, kModeRestrict = 1, kModeAw = 2 };
 
 __device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
+// T = float only in RESTRICT mode (the finest grid of an FP32 cycle)
+template <typename T>
 struct MarchArgs {
-  const double* p;    // p, or d in AW mode
-  const double* f;    // NORM / RESTRICT
-  const double* bx;
-  const double* by;
-  const double* bz;
-  const double* rt;
+  const T* p;         // p, or d in AW mode
+  const T* f;         // NORM / RESTRICT
+  const T* bx;
+  const T* by;
+  const T* bz;
+  const T* rt;
   const double* fshift;
   int q, kc;
-  double inv_h2;
+  T inv_h2;
   // NORM
   float* r32;
   float* e32;
@@ -54,8 +58,8 @@ struct MarchArgs {
   double* z64;
   double* partials;   // NORM: r^2; AW: d.w
   // RESTRICT
-  double* fc;
-  double* ec;
+  T* fc;
+  T* ec;
   // AW
   const double* r;
   double* w;
@@ -63,23 +67,24 @@ struct MarchArgs {
 };
 
 // The six faces of the two cells of an x-pair
+template <typename T>
 struct PF {
-  double x0, x1, x2, ym0, ym1, yp0, yp1, zm0, zm1, zp0, zp1;
+  T x0, x1, x2, ym0, ym1, yp0, yp1, zm0, zm1, zp0, zp1;
 };
 
 // r of the two cells of a pair from p at the cell, its x neighbours (pl, pr), the pair
 // in the rows below / above and the planes below / above
-__device__ __forceinline__ void pair_r(const PF& F, double2 pc, double pl, double pr, double2 pyd, double2 pyu,
-                                       double2 pzd, double2 pzu, double2 fv, double fs, double inv_h2, double& r0,
-                                       double& r1) {
-  const double D0 = F.x0 + F.x1 + F.ym0 + F.yp0 + F.zm0 + F.zp0;
-  const double D1 = F.x1 + F.x2 + F.ym1 + F.yp1 + F.zm1 + F.zp1;
-  const double s0 = fmad(F.zp0, pzu.x - pc.x, fmad(F.zm0, pzd.x - pc.x, fmad(F.yp0, pyu.x - pc.x,
+template <typename T, typename V2 = typename Vec2<T>::type>
+__device__ __forceinline__ void pair_r(const PF<T>& F, V2 pc, T pl, T pr, V2 pyd, V2 pyu, V2 pzd, V2 pzu, V2 fv, T fs,
+                                       T inv_h2, T& r0, T& r1) {
+  const T D0 = F.x0 + F.x1 + F.ym0 + F.yp0 + F.zm0 + F.zp0;
+  const T D1 = F.x1 + F.x2 + F.ym1 + F.yp1 + F.zm1 + F.zp1;
+  const T s0 = fmad(F.zp0, pzu.x - pc.x, fmad(F.zm0, pzd.x - pc.x, fmad(F.yp0, pyu.x - pc.x,
                     fmad(F.ym0, pyd.x - pc.x, fmad(F.x1, pc.y - pc.x, F.x0 * (pl - pc.x))))));
-  const double s1 = fmad(F.zp1, pzu.y - pc.y, fmad(F.zm1, pzd.y - pc.y, fmad(F.yp1, pyu.y - pc.y,
+  const T s1 = fmad(F.zp1, pzu.y - pc.y, fmad(F.zm1, pzd.y - pc.y, fmad(F.yp1, pyu.y - pc.y,
                     fmad(F.ym1, pyd.y - pc.y, fmad(F.x2, pr - pc.y, F.x1 * (pc.x - pc.y))))));
-  r0 = D0 > 0.0 ? fmad(-inv_h2, s0, fv.x - fs) : 0.0;
-  r1 = D1 > 0.0 ? fmad(-inv_h2, s1, fv.y - fs) : 0.0;
+  r0 = D0 > T(0) ? fmad(-inv_h2, s0, fv.x - fs) : T(0);
+  r1 = D1 > T(0) ? fmad(-inv_h2, s1, fv.y - fs) : T(0);
 }
 
 __device__ __forceinline__ double block_sum(double v) {
@@ -94,13 +99,16 @@ __device__ __forceinline__ double block_sum(double v) {
   return s;   // valid in thread 0
 }
 
-template <bool RHO, int MODE, int TX>
-__global__ __launch_bounds__(kMarchThreads) void k_residual_march(MarchArgs a) {
+template <typename T, bool RHO, int MODE, int TX>
+__global__ __launch_bounds__(kMarchThreads) void k_residual_march(MarchArgs<T> a) {
+  using V2 = typename Vec2<T>::type;
+  static_assert(sizeof(T) == 8 || MODE == kModeRestrict, "FP32 marches restrict only");
   constexpr int PAIRS = TX / 2;                 // x-pairs per tile row
   constexpr int RP = kMarchThreads / PAIRS;     // row pairs per tile
   constexpr int TY = 2 * RP;
   const int q = a.q, n = 1 << q;
-  const double inf = __builtin_huge_val();
+  const T inf = __builtin_huge_val();
+  const T zero = T(0);
   const int tid = threadIdx.x;
   const int G = gridDim.x, bid = blockIdx.x;
   const int lid = (G % 8 == 0) ? (bid % 8) * (G / 8) + bid / 8 : bid;   // neighbours on one XCD
@@ -110,54 +118,55 @@ __global__ __launch_bounds__(kMarchThreads) void k_residual_march(MarchArgs a) {
   const int k0 = (lid / (ntx * nty)) * a.kc;
   const int ip = i0 + 2 * (tid % PAIRS);
   const int ja = j0 + 2 * (tid / PAIRS), jb = ja + 1;
-  const unsigned oa = off_of<double>(ip, ja, q), ob = off_of<double>(ip, jb, q);
-  const unsigned od = off_of<double>(ip, ja - 1, q), ou = off_of<double>(ip, jb + 1, q);
-  const unsigned ola = off_of<double>(ip - 1, ja, q), ora = off_of<double>(ip + 2, ja, q);
-  const unsigned olb = off_of<double>(ip - 1, jb, q), orb = off_of<double>(ip + 2, jb, q);
-  const double fs = (MODE != kModeAw && a.fshift) ? *a.fshift : 0.0;
+  const unsigned oa = off_of<T>(ip, ja, q), ob = off_of<T>(ip, jb, q);
+  const unsigned od = off_of<T>(ip, ja - 1, q), ou = off_of<T>(ip, jb + 1, q);
+  const unsigned ola = off_of<T>(ip - 1, ja, q), ora = off_of<T>(ip + 2, ja, q);
+  const unsigned olb = off_of<T>(ip - 1, jb, q), orb = off_of<T>(ip + 2, jb, q);
+  const T fs = (MODE != kModeAw && a.fshift) ? static_cast<T>(*a.fshift) : zero;
 
   // window: the pair's p on the planes below, at and above the current one (rows a, b)
   const Rsrc p_lo = plane_rsrc(a.p, k0 - 1, q), p_c = plane_rsrc(a.p, k0, q);
-  double2 pa_lo = ld2(p_lo, oa, 0.0), pb_lo = ld2(p_lo, ob, 0.0);
-  double2 pa = ld2(p_c, oa, 0.0), pb = ld2(p_c, ob, 0.0);
+  V2 pa_lo = ld2(p_lo, oa, zero), pb_lo = ld2(p_lo, ob, zero);
+  V2 pa = ld2(p_c, oa, zero), pb = ld2(p_c, ob, zero);
   // faces to the plane below (carried), and for the density form the pair's density
-  double2 za, zb;                 // zm of rows a, b on the current plane
-  double2 ra, rb;                 // density form: rt of the pair on the current plane
+  V2 za, zb;                 // zm of rows a, b on the current plane
+  V2 ra, rb;                 // density form: rt of the pair on the current plane
   if constexpr (RHO) {
     const bool in_lo = k0 >= 1;
-    const double2 la = ld2(plane_rsrc(a.rt, k0 - 1, q), oa, 0.0), lb = ld2(plane_rsrc(a.rt, k0 - 1, q), ob, 0.0);
-    ra = ld2(plane_rsrc(a.rt, k0, q), oa, 0.0);
-    rb = ld2(plane_rsrc(a.rt, k0, q), ob, 0.0);
-    za = in_lo ? double2{face_beta(la.x, ra.x), face_beta(la.y, ra.y)} : double2{0.0, 0.0};
-    zb = in_lo ? double2{face_beta(lb.x, rb.x), face_beta(lb.y, rb.y)} : double2{0.0, 0.0};
+    const V2 la = ld2(plane_rsrc(a.rt, k0 - 1, q), oa, zero), lb = ld2(plane_rsrc(a.rt, k0 - 1, q), ob, zero);
+    ra = ld2(plane_rsrc(a.rt, k0, q), oa, zero);
+    rb = ld2(plane_rsrc(a.rt, k0, q), ob, zero);
+    za = in_lo ? V2{face_beta(la.x, ra.x), face_beta(la.y, ra.y)} : V2{zero, zero};
+    zb = in_lo ? V2{face_beta(lb.x, rb.x), face_beta(lb.y, rb.y)} : V2{zero, zero};
   } else {
     const Rsrc zk = plane_rsrc(a.bz, k0, q);
-    za = ld2(zk, oa, 0.0);   // 0 on the bottom wall (stored) and below the grid
-    zb = ld2(zk, ob, 0.0);
+    za = ld2(zk, oa, zero);   // 0 on the bottom wall (stored) and below the grid
+    zb = ld2(zk, ob, zero);
   }
-  double acc = 0.0, acc2 = 0.0, csum = 0.0;
+  double acc = 0.0, acc2 = 0.0;
+  T csum = zero;
   for (int k = k0; k < k0 + a.kc; ++k) {
     const Rsrc pk = plane_rsrc(a.p, k, q), pu = plane_rsrc(a.p, k + 1, q);
-    const double2 pa_hi = ld2(pu, oa, 0.0), pb_hi = ld2(pu, ob, 0.0);   // 0 above the grid
-    const double2 pd = ld2(pk, od, 0.0), pup = ld2(pk, ou, 0.0);
-    const double pla = ld1(pk, ola, 0.0), pra = ld1(pk, ora, 0.0);
-    const double plb = ld1(pk, olb, 0.0), prb = ld1(pk, orb, 0.0);
-    double2 fa{0.0, 0.0}, fb{0.0, 0.0};
+    const V2 pa_hi = ld2(pu, oa, zero), pb_hi = ld2(pu, ob, zero);   // 0 above the grid
+    const V2 pd = ld2(pk, od, zero), pup = ld2(pk, ou, zero);
+    const T pla = ld1(pk, ola, zero), pra = ld1(pk, ora, zero);
+    const T plb = ld1(pk, olb, zero), prb = ld1(pk, orb, zero);
+    V2 fa{zero, zero}, fb{zero, zero};
     if constexpr (MODE != kModeAw) {
       const Rsrc fk = plane_rsrc(a.f, k, q);
-      fa = ld2(fk, oa, 0.0);
-      fb = ld2(fk, ob, 0.0);
+      fa = ld2(fk, oa, zero);
+      fb = ld2(fk, ob, zero);
     }
-    PF Fa, Fb;
-    double2 za_next, zb_next;
+    PF<T> Fa, Fb;
+    V2 za_next, zb_next;
     if constexpr (RHO) {
       const Rsrc rk = plane_rsrc(a.rt, k, q), rup = plane_rsrc(a.rt, k + 1, q);
       const bool in_hi = k + 1 < n;
-      const double2 ha = ld2(rup, oa, 0.0), hb = ld2(rup, ob, 0.0);
-      const double2 rd = ld2(rk, od, 0.0), rup2 = ld2(rk, ou, 0.0);
-      const double rla = ld1(rk, ola, 0.0), rra = ld1(rk, ora, 0.0), rlb = ld1(rk, olb, 0.0), rrb = ld1(rk, orb, 0.0);
-      const double2 ha_i{in_hi ? ha.x : inf, in_hi ? ha.y : inf}, hb_i{in_hi ? hb.x : inf, in_hi ? hb.y : inf};
-      const double mid0 = face_beta(ra.x, rb.x), mid1 = face_beta(ra.y, rb.y);   // between rows a and b
+      const V2 ha = ld2(rup, oa, zero), hb = ld2(rup, ob, zero);
+      const V2 rd = ld2(rk, od, zero), rup2 = ld2(rk, ou, zero);
+      const T rla = ld1(rk, ola, zero), rra = ld1(rk, ora, zero), rlb = ld1(rk, olb, zero), rrb = ld1(rk, orb, zero);
+      const V2 ha_i{in_hi ? ha.x : inf, in_hi ? ha.y : inf}, hb_i{in_hi ? hb.x : inf, in_hi ? hb.y : inf};
+      const T mid0 = face_beta(ra.x, rb.x), mid1 = face_beta(ra.y, rb.y);   // between rows a and b
       Fa.x0 = face_beta(rla, ra.x);
       Fa.x1 = face_beta(ra.x, ra.y);
       Fa.x2 = face_beta(ra.y, rra);
@@ -180,25 +189,25 @@ __global__ __launch_bounds__(kMarchThreads) void k_residual_march(MarchArgs a) {
       Fb.zm1 = zb.y;
       Fb.zp0 = face_beta(rb.x, hb_i.x);
       Fb.zp1 = face_beta(rb.y, hb_i.y);
-      za_next = double2{Fa.zp0, Fa.zp1};
-      zb_next = double2{Fb.zp0, Fb.zp1};
+      za_next = V2{Fa.zp0, Fa.zp1};
+      zb_next = V2{Fb.zp0, Fb.zp1};
       ra = ha;
       rb = hb;
     } else {
       const Rsrc xk = plane_rsrc(a.bx, k, q), yk = plane_rsrc(a.by, k, q), zu = plane_rsrc(a.bz, k + 1, q);
-      const double2 bxa = ld2(xk, oa, 0.0), bxb = ld2(xk, ob, 0.0);
-      const double bxra = ld1(xk, ora, 0.0), bxrb = ld1(xk, orb, 0.0);
-      const double2 bya = ld2(yk, oa, 0.0), byb = ld2(yk, ob, 0.0), byu = ld2(yk, ou, 0.0);
-      za_next = ld2(zu, oa, 0.0);   // 0 above the grid (top wall)
-      zb_next = ld2(zu, ob, 0.0);
-      Fa = PF{bxa.x, bxa.y, bxra, bya.x, bya.y, byb.x, byb.y, za.x, za.y, za_next.x, za_next.y};
-      Fb = PF{bxb.x, bxb.y, bxrb, byb.x, byb.y, byu.x, byu.y, zb.x, zb.y, zb_next.x, zb_next.y};
+      const V2 bxa = ld2(xk, oa, zero), bxb = ld2(xk, ob, zero);
+      const T bxra = ld1(xk, ora, zero), bxrb = ld1(xk, orb, zero);
+      const V2 bya = ld2(yk, oa, zero), byb = ld2(yk, ob, zero), byu = ld2(yk, ou, zero);
+      za_next = ld2(zu, oa, zero);   // 0 above the grid (top wall)
+      zb_next = ld2(zu, ob, zero);
+      Fa = PF<T>{bxa.x, bxa.y, bxra, bya.x, bya.y, byb.x, byb.y, za.x, za.y, za_next.x, za_next.y};
+      Fb = PF<T>{bxb.x, bxb.y, bxrb, byb.x, byb.y, byu.x, byu.y, zb.x, zb.y, zb_next.x, zb_next.y};
     }
-    double r0a, r1a, r0b, r1b;
+    T r0a, r1a, r0b, r1b;
     pair_r(Fa, pa, pla, pra, pd, pb, pa_lo, pa_hi, fa, fs, a.inv_h2, r0a, r1a);
     pair_r(Fb, pb, plb, prb, pa, pup, pb_lo, pb_hi, fb, fs, a.inv_h2, r0b, r1b);
     const long long plane = static_cast<long long>(k) << (2 * q);
-    const long long ca = plane + (oa >> 3), cb = plane + (ob >> 3);
+    const long long ca = plane + oa / sizeof(T), cb = plane + ob / sizeof(T);
     if constexpr (MODE == kModeNorm) {
       acc = fmad(r1a, r1a, fmad(r0a, r0a, acc));
       acc = fmad(r1b, r1b, fmad(r0b, r0b, acc));
@@ -221,14 +230,14 @@ __global__ __launch_bounds__(kMarchThreads) void k_residual_march(MarchArgs a) {
     } else if constexpr (MODE == kModeRestrict) {
       // children in the order of every other restriction: (row a, plane 2K),
       // (row b, plane 2K), (row a, plane 2K+1), (row b, plane 2K+1)
-      if ((k & 1) == 0) csum = 0.0;
+      if ((k & 1) == 0) csum = zero;
       csum += r0a + r1a;
       csum += r0b + r1b;
       if (k & 1) {
         const int qc = q - 1;
         const int C = ((((k >> 1) << qc) | (ja >> 1)) << qc) | (ip >> 1);
-        a.fc[C] = csum * 0.125;
-        a.ec[C] = 0.0;
+        a.fc[C] = csum * T(0.125);
+        a.ec[C] = zero;
       }
     } else {
       // the residual of f = 0 is -A d
@@ -262,8 +271,8 @@ __global__ __launch_bounds__(kMarchThreads) void k_residual_march(MarchArgs a) {
   }
 }
 
-template <bool RHO, int MODE>
-hipError_t launch_mode(MarchArgs a, int* nblocks, hipStream_t s) {
+template <typename T, bool RHO, int MODE>
+hipError_t launch_mode(MarchArgs<T> a, int* nblocks, hipStream_t s) {
   const int n = 1 << a.q;
   const int TX = n >= 128 ? 128 : n;
   const int TY = 2 * (kMarchThreads / (TX / 2));
@@ -278,17 +287,17 @@ hipError_t launch_mode(MarchArgs a, int* nblocks, hipStream_t s) {
   *nblocks = blocks;
   const dim3 grid(blocks), block(kMarchThreads);
   if (TX == 128)
-    hipLaunchKernelGGL((k_residual_march<RHO, MODE, 128>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((k_residual_march<T, RHO, MODE, 128>), grid, block, 0, s, a);
   else if (TX == 64)
-    hipLaunchKernelGGL((k_residual_march<RHO, MODE, 64>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((k_residual_march<T, RHO, MODE, 64>), grid, block, 0, s, a);
   else
-    hipLaunchKernelGGL((k_residual_march<RHO, MODE, 32>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((k_residual_march<T, RHO, MODE, 32>), grid, block, 0, s, a);
   return hipGetLastError();
 }
 
-template <int MODE>
-hipError_t launch_form(MarchArgs a, int* nblocks, hipStream_t s) {
-  return a.rt ? launch_mode<true, MODE>(a, nblocks, s) : launch_mode<false, MODE>(a, nblocks, s);
+template <int MODE, typename T>
+hipError_t launch_form(MarchArgs<T> a, int* nblocks, hipStream_t s) {
+  return a.rt ? launch_mode<T, true, MODE>(a, nblocks, s) : launch_mode<T, false, MODE>(a, nblocks, s);
 }
 
 }  // namespace
@@ -299,7 +308,7 @@ hipError_t launch_residual_norm_march(const double* p, const double* f, const do
                                       const double* bz, const double* rt, int q, double h, const double* fshift,
                                       float* r32, float* e32, double* r64, double* z64, double* partials,
                                       int* nblocks, hipStream_t s) {
-  MarchArgs a{};
+  MarchArgs<double> a{};
   a.p = p;
   a.f = f;
   a.bx = bx;
@@ -317,10 +326,10 @@ hipError_t launch_residual_norm_march(const double* p, const double* f, const do
   return launch_form<kModeNorm>(a, nblocks, s);
 }
 
-hipError_t launch_residual_restrict_march(const double* p, const double* f, const double* bx, const double* by,
-                                          const double* bz, const double* rt, int q, double h, const double* fshift,
-                                          double* fc, double* ec, hipStream_t s) {
-  MarchArgs a{};
+template <typename T>
+hipError_t launch_residual_restrict_march(const T* p, const T* f, const T* bx, const T* by, const T* bz, const T* rt,
+                                          int q, double h, const double* fshift, T* fc, T* ec, hipStream_t s) {
+  MarchArgs<T> a{};
   a.p = p;
   a.f = f;
   a.bx = bx;
@@ -336,10 +345,17 @@ hipError_t launch_residual_restrict_march(const double* p, const double* f, cons
   return launch_form<kModeRestrict>(a, &nb, s);
 }
 
+template hipError_t launch_residual_restrict_march<double>(const double*, const double*, const double*, const double*,
+                                                           const double*, const double*, int, double, const double*,
+                                                           double*, double*, hipStream_t);
+template hipError_t launch_residual_restrict_march<float>(const float*, const float*, const float*, const float*,
+                                                          const float*, const float*, int, double, const double*,
+                                                          float*, float*, hipStream_t);
+
 hipError_t launch_fcg_aw_march(const double* d, const double* r, const double* bx, const double* by, const double* bz,
                                const double* rt, int q, double h, double* w, double* part_dw, double* part_dr,
                                int* nblocks, hipStream_t s) {
-  MarchArgs a{};
+  MarchArgs<double> a{};
   a.p = d;
   a.bx = bx;
   a.by = by;
