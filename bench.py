@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device copy (HBM counter calibration) and exit")
+    ap.add_argument("--oracle-timing", action="store_true",
+                    help="only time the CPU oracle on this host (multigrid 32^3..256^3, FFT+Thomas 512^3) and exit")
     return ap.parse_args()
 
 
@@ -55,6 +57,9 @@ def main():
         print(json.dumps({"error": "this solver runs on one GPU; multi-GPU runs are not supported",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.oracle_timing:
+        print(json.dumps(oracle_timing()))
+        return
     import numpy as np
     import torch
 
@@ -282,6 +287,47 @@ def cpu_baseline(inp):
             "sample": f"{cycles} FP64 V(2,2) cycles of the numpy oracle on the same {inp.N}^3 workload "
                       f"(setup {t_setup:.1f} s excluded); numpy elementwise kernels are single-threaded",
             "host_cpus": os.cpu_count()}
+
+
+def oracle_timing():
+    """The CPU oracle on this host, the baseline beside the GPU numbers: FP64 multigrid
+    per V(2,2) cycle and to a relative residual of 1e-10 from p = 0 on the bench field
+    (wavy interface + body) at 32^3 .. 256^3, and the FFT + Thomas direct solve of the
+    512^3 flat field (a different algorithm: exact, not iterative).  numpy's elementwise
+    kernels and numpy.fft run on one thread."""
+    import numpy as np
+
+    import fields
+    from oracle import exact
+    from oracle import multigrid as omg
+    from oracle.operator import Level, face_coeffs_from_rho, project
+    rows = []
+    for N in (32, 64, 128, 256):
+        inp = fields.make("c2", N)
+        t0 = time.time()
+        H = omg.setup(*face_coeffs_from_rho(inp.rho, inp.mask), inp.mask, inp.h)
+        t_setup = time.time() - t0
+        fh = project(inp.f, H.fine.mask)
+        p = np.zeros_like(fh)
+        reps = 2 if N >= 256 else 3
+        t0 = time.time()
+        for _ in range(reps):
+            p = omg.vcycle(H, p, fh)
+        t_cycle = (time.time() - t0) / reps
+        t0 = time.time()
+        _, hist = omg.solve(H, inp.f, tol=1e-10, max_cycles=100)
+        t_solve = time.time() - t0
+        rows.append({"N": N, "setup_s": t_setup, "vcycle_s": t_cycle, "grid_pts_per_s": inp.n / t_cycle,
+                     "cycles_to_1e-10": len(hist) - 1, "solve_s": t_solve})
+        log(f"oracle {N}^3: V-cycle {t_cycle:.3f} s, {len(hist) - 1} cycles to 1e-10 in {t_solve:.1f} s")
+    inp = fields.make("c3", 512)
+    lev = Level(*face_coeffs_from_rho(inp.rho, inp.mask), inp.mask.astype(bool), inp.h)
+    t0 = time.time()
+    exact.solve_fft_z(lev, inp.f)
+    t_fft = time.time() - t0
+    log(f"oracle 512^3 FFT + Thomas: {t_fft:.1f} s")
+    return {"oracle_timing": {"host_cpus": os.cpu_count(), "threads_used": 1, "multigrid_c2": rows,
+                              "fft_thomas_c3_512": {"solve_s": t_fft, "algorithm": "direct (FFT in x, y; Thomas in z)"}}}
 
 
 if __name__ == "__main__":
