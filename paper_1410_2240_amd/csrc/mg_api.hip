@@ -325,16 +325,32 @@ int solve_one(mg_ctx* c, const double* f, double* p, double tol, int max_cycles,
       MG_HIP(mg::launch_fcg_dir(z64, z32, kd, c->scal + S_ZW, c->scal + S_DW, q, c->stream));
     }
   }
+  // Mixed refinement on a density-form finest grid: the FP64 update p + e and the next
+  // residual in one pass, p alternating with the finest grid's second FP64 buffer (free
+  // while the cycles run in FP32); the last iterate is copied back into p below.  Only
+  // where the pass need not also clear e32 (one-pass-swept grids), since it reads e32.
+  const bool fuse_update = mixed && a.rt && mg::march_supported(a.q) && e32_zero == nullptr;
+  double* cur = p;
   while (!(c->flags & MG_KRYLOV) && std::isfinite(r) && r > tol && *cycles < max_cycles) {
     if (mixed) {
       // FP32 V-cycle for the correction from the FP32 copy of the FP64 residual, FP64 update
       MG_TRY(vcycle<float>(c, 0, e32, r32, nullptr, true));
-      MG_HIP(mg::launch_update_p(p, e32, a.mask, a.q, c->stream));
+      if (fuse_update) {
+        double* next = cur == p ? a.t : p;
+        int nbu = 0;
+        MG_HIP(mg::launch_residual_norm_update_march(cur, e32, next, f, a.rt, a.q, a.h, fshift, r32, e32_zero,
+                                                     c->partials, &nbu, c->stream));
+        MG_TRY(reduce(c, nbu, 1.0, S_RNORM2));
+        cur = next;
+      } else {
+        MG_HIP(mg::launch_update_p(p, e32, a.mask, a.q, c->stream));
+        MG_TRY(residual_norm(c, p, f, fshift, r32, e32_zero));
+      }
     } else {
       MG_TRY(vcycle<double>(c, 0, p, f, fshift));
+      MG_TRY(residual_norm(c, p, f, fshift, r32, e32_zero));
     }
     ++*cycles;
-    MG_TRY(residual_norm(c, p, f, fshift, r32, e32_zero));
     double sn[3];
     MG_TRY(read_scalars(c, sn, 3));
     r = std::sqrt(sn[S_RNORM2]) / nf;
@@ -345,6 +361,7 @@ int solve_one(mg_ctx* c, const double* f, double* p, double tol, int max_cycles,
       break;
     }
   }
+  if (cur != p) MG_HIP(hipMemcpyAsync(p, cur, sizeof(double) * cells(a), hipMemcpyDeviceToDevice, c->stream));
   if (status == MG_OK && r > tol)
     status = fail(MG_ENOCONV, "relative residual %g > tol %g after %d cycles", r, tol, *cycles);
   // gauge: zero fluid mean, 0 in the body

@@ -133,6 +133,13 @@ hipError_t launch_residual_norm_march(const double* p, const double* f, const do
 template <typename T>
 hipError_t launch_residual_restrict_march(const T* p, const T* f, const T* bx, const T* by, const T* bz, const T* rt,
                                           int q, double h, const double* fshift, T* fc, T* ec, hipStream_t s);
+// p + e (e in FP32, added on active cells) written to pout, and the norm pass of that
+// sum: partials, r32, e32 as launch_residual_norm_march.  The density form only (rt is
+// required); pout must not overlap p, and e32 (cleared) must be null or not overlap e.  The update and residual of one mixed-precision
+// refinement step in one pass.
+hipError_t launch_residual_norm_update_march(const double* p, const float* e, double* pout, const double* f,
+                                             const double* rt, int q, double h, const double* fshift, float* r32,
+                                             float* e32, double* partials, int* nblocks, hipStream_t s);
 hipError_t launch_fcg_aw_march(const double* d, const double* r, const double* bx, const double* by, const double* bz,
                                const double* rt, int q, double h, double* w, double* part_dw, double* part_dr,
                                int* nblocks, hipStream_t s);

@@ -34,7 +34,7 @@ using buf::Rsrc;
 using buf::Vec2;
 
 constexpr int kMarchThreads = 256;
-enum { kModeNorm = 0, kModeRestrict = 1, kModeAw = 2 };
+enum { kModeNorm = 0, kModeRestrict = 1, kModeAw = 2, kModeNormUpdate = 3 };
 
 __device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
@@ -64,6 +64,10 @@ struct MarchArgs {
   const double* r;
   double* w;
   double* partials2;  // AW: d.r
+  // NORM with update: the residual of p + e (e in FP32, added on active cells), and
+  // p + e written to pout
+  const float* eu;
+  double* pout;
 };
 
 // The six faces of the two cells of an x-pair
@@ -87,6 +91,14 @@ __device__ __forceinline__ void pair_r(const PF<T>& F, V2 pc, T pl, T pr, V2 pyd
   r1 = D1 > T(0) ? fmad(-inv_h2, s1, fv.y - fs) : T(0);
 }
 
+// p + e on active cells (density finite); the update of a mixed-precision refinement step
+__device__ __forceinline__ double add_active(double p, float e, double rt) {
+  return rt < __builtin_huge_val() ? p + static_cast<double>(e) : p;
+}
+__device__ __forceinline__ double2 add_active(double2 p, float2 e, double2 rt) {
+  return double2{add_active(p.x, e.x, rt.x), add_active(p.y, e.y, rt.y)};
+}
+
 __device__ __forceinline__ double block_sum(double v) {
   __shared__ double red[kMarchThreads / 64];
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -103,6 +115,9 @@ template <typename T, bool RHO, int MODE, int TX>
 __global__ __launch_bounds__(kMarchThreads) void k_residual_march(MarchArgs<T> a) {
   using V2 = typename Vec2<T>::type;
   static_assert(sizeof(T) == 8 || MODE == kModeRestrict, "FP32 marches restrict only");
+  constexpr bool UPD = MODE == kModeNormUpdate;
+  constexpr bool NORM = MODE == kModeNorm || UPD;
+  static_assert(!UPD || RHO, "the update mode reads activity from the density form");
   constexpr int PAIRS = TX / 2;                 // x-pairs per tile row
   constexpr int RP = kMarchThreads / PAIRS;     // row pairs per tile
   constexpr int TY = 2 * RP;
@@ -138,6 +153,13 @@ __global__ __launch_bounds__(kMarchThreads) void k_residual_march(MarchArgs<T> a
     rb = ld2(plane_rsrc(a.rt, k0, q), ob, zero);
     za = in_lo ? V2{face_beta(la.x, ra.x), face_beta(la.y, ra.y)} : V2{zero, zero};
     zb = in_lo ? V2{face_beta(lb.x, rb.x), face_beta(lb.y, rb.y)} : V2{zero, zero};
+    if constexpr (UPD) {
+      const Rsrc e_lo = plane_rsrc(a.eu, k0 - 1, q), e_c = plane_rsrc(a.eu, k0, q);
+      pa_lo = add_active(pa_lo, ld2(e_lo, oa >> 1, 0.0f), la);
+      pb_lo = add_active(pb_lo, ld2(e_lo, ob >> 1, 0.0f), lb);
+      pa = add_active(pa, ld2(e_c, oa >> 1, 0.0f), ra);
+      pb = add_active(pb, ld2(e_c, ob >> 1, 0.0f), rb);
+    }
   } else {
     const Rsrc zk = plane_rsrc(a.bz, k0, q);
     za = ld2(zk, oa, zero);   // 0 on the bottom wall (stored) and below the grid
@@ -147,10 +169,23 @@ __global__ __launch_bounds__(kMarchThreads) void k_residual_march(MarchArgs<T> a
   T csum = zero;
   for (int k = k0; k < k0 + a.kc; ++k) {
     const Rsrc pk = plane_rsrc(a.p, k, q), pu = plane_rsrc(a.p, k + 1, q);
-    const V2 pa_hi = ld2(pu, oa, zero), pb_hi = ld2(pu, ob, zero);   // 0 above the grid
-    const V2 pd = ld2(pk, od, zero), pup = ld2(pk, ou, zero);
-    const T pla = ld1(pk, ola, zero), pra = ld1(pk, ora, zero);
-    const T plb = ld1(pk, olb, zero), prb = ld1(pk, orb, zero);
+    V2 pa_hi = ld2(pu, oa, zero), pb_hi = ld2(pu, ob, zero);   // 0 above the grid
+    V2 pd = ld2(pk, od, zero), pup = ld2(pk, ou, zero);
+    T pla = ld1(pk, ola, zero), pra = ld1(pk, ora, zero);
+    T plb = ld1(pk, olb, zero), prb = ld1(pk, orb, zero);
+    float2 ea_hi, eb_hi, ed, eup;   // UPD: the correction at the same places
+    float ela, era, elb, erb;
+    if constexpr (UPD) {
+      const Rsrc ek = plane_rsrc(a.eu, k, q), eup_k = plane_rsrc(a.eu, k + 1, q);
+      ea_hi = ld2(eup_k, oa >> 1, 0.0f);
+      eb_hi = ld2(eup_k, ob >> 1, 0.0f);
+      ed = ld2(ek, od >> 1, 0.0f);
+      eup = ld2(ek, ou >> 1, 0.0f);
+      ela = ld1(ek, ola >> 1, 0.0f);
+      era = ld1(ek, ora >> 1, 0.0f);
+      elb = ld1(ek, olb >> 1, 0.0f);
+      erb = ld1(ek, orb >> 1, 0.0f);
+    }
     V2 fa{zero, zero}, fb{zero, zero};
     if constexpr (MODE != kModeAw) {
       const Rsrc fk = plane_rsrc(a.f, k, q);
@@ -165,6 +200,16 @@ __global__ __launch_bounds__(kMarchThreads) void k_residual_march(MarchArgs<T> a
       const V2 ha = ld2(rup, oa, zero), hb = ld2(rup, ob, zero);
       const V2 rd = ld2(rk, od, zero), rup2 = ld2(rk, ou, zero);
       const T rla = ld1(rk, ola, zero), rra = ld1(rk, ora, zero), rlb = ld1(rk, olb, zero), rrb = ld1(rk, orb, zero);
+      if constexpr (UPD) {
+        pa_hi = add_active(pa_hi, ea_hi, ha);
+        pb_hi = add_active(pb_hi, eb_hi, hb);
+        pd = add_active(pd, ed, rd);
+        pup = add_active(pup, eup, rup2);
+        pla = add_active(pla, ela, rla);
+        pra = add_active(pra, era, rra);
+        plb = add_active(plb, elb, rlb);
+        prb = add_active(prb, erb, rrb);
+      }
       const V2 ha_i{in_hi ? ha.x : inf, in_hi ? ha.y : inf}, hb_i{in_hi ? hb.x : inf, in_hi ? hb.y : inf};
       const T mid0 = face_beta(ra.x, rb.x), mid1 = face_beta(ra.y, rb.y);   // between rows a and b
       Fa.x0 = face_beta(rla, ra.x);
@@ -208,7 +253,11 @@ __global__ __launch_bounds__(kMarchThreads) void k_residual_march(MarchArgs<T> a
     pair_r(Fb, pb, plb, prb, pa, pup, pb_lo, pb_hi, fb, fs, a.inv_h2, r0b, r1b);
     const long long plane = static_cast<long long>(k) << (2 * q);
     const long long ca = plane + oa / sizeof(T), cb = plane + ob / sizeof(T);
-    if constexpr (MODE == kModeNorm) {
+    if constexpr (NORM) {
+      if constexpr (UPD) {
+        *reinterpret_cast<double2*>(a.pout + ca) = pa;
+        *reinterpret_cast<double2*>(a.pout + cb) = pb;
+      }
       acc = fmad(r1a, r1a, fmad(r0a, r0a, acc));
       acc = fmad(r1b, r1b, fmad(r0b, r0b, acc));
       if (a.r32) {
@@ -257,7 +306,7 @@ __global__ __launch_bounds__(kMarchThreads) void k_residual_march(MarchArgs<T> a
     za = za_next;
     zb = zb_next;
   }
-  if constexpr (MODE == kModeNorm) {
+  if constexpr (NORM) {
     const double s = block_sum(acc);
     if (tid == 0) a.partials[bid] = s;
   } else if constexpr (MODE == kModeAw) {
@@ -343,6 +392,25 @@ hipError_t launch_residual_restrict_march(const T* p, const T* f, const T* bx, c
   a.ec = ec;
   int nb = 0;
   return launch_form<kModeRestrict>(a, &nb, s);
+}
+
+hipError_t launch_residual_norm_update_march(const double* p, const float* e, double* pout, const double* f,
+                                             const double* rt, int q, double h, const double* fshift, float* r32,
+                                             float* e32, double* partials, int* nblocks, hipStream_t s) {
+  if (!rt || p == pout || e == e32) return hipErrorInvalidValue;
+  MarchArgs<double> a{};
+  a.p = p;
+  a.f = f;
+  a.rt = rt;
+  a.fshift = fshift;
+  a.q = q;
+  a.inv_h2 = 1.0 / (h * h);
+  a.r32 = r32;
+  a.e32 = e32;
+  a.partials = partials;
+  a.eu = e;
+  a.pout = pout;
+  return launch_mode<double, true, kModeNormUpdate>(a, nblocks, s);
 }
 
 template hipError_t launch_residual_restrict_march<double>(const double*, const double*, const double*, const double*,
