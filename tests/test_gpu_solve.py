@@ -176,6 +176,29 @@ def test_batch_and_warm_start():
     assert len(h2) == 1   # already converged
 
 
+def test_mixed_batch_and_warm_start_64():
+    """Mixed refinement on a 64^3 density-form grid, where each step's FP64 update is
+    formed inside the next residual pass and the iterate alternates between the caller's
+    p and the solver's second buffer: a batch of three right-hand sides against the
+    exact solutions, solves that end in either buffer, and warm starts."""
+    from paper_1410_2240_amd import MG
+    inp, H = workload("c1", 64)
+    mg = MG.from_rho(dev(inp.rho), dev(inp.mask), mixed=True)
+    fb = fields.batch_rhs(inp.mask, 3)
+    p, hists, st = mg.solve(dev(fb), tol=1e-12)
+    for b in range(3):
+        assert relerr(host(p[b]), exact.solve_fft_z(H.fine, fb[b])) <= 1e-9
+    steps = {len(h) - 1 for h in hists}
+    # from a rough warm start, an odd and an even number of steps
+    for tol in (1e-6, 1e-7, 1e-8):
+        q, hq, _ = mg.solve(dev(fb[0]), tol=tol)
+        steps.add(len(hq) - 1)
+        w, hw, _ = mg.solve(dev(fb[0]), p=q.clone(), tol=1e-12)
+        assert relerr(host(w), exact.solve_fft_z(H.fine, fb[0])) <= 1e-9
+        assert len(hw) < len(hists[0])
+    assert any(s % 2 for s in steps) and any(s % 2 == 0 for s in steps), steps
+
+
 # ------------------------------------------------------------------ error paths
 
 def test_errors_reported():
