@@ -149,6 +149,9 @@ int mg_set_stream(mg_ctx* ctx, void* hip_stream);
  * fluid mean and 0 in the body.  hist (HOST, may be NULL) receives batch rows of
  * max_cycles+1 relative residuals, hist[b*(max_cycles+1)+0] for the initial guess;
  * n_hist (HOST, may be NULL) receives the entries written per item.  stats may be NULL.
+ * A right-hand side whose projection is zero to rounding (||P f|| <= 64 eps ||f|| over
+ * the fluid cells, eps = 2^-52, e.g. f = 0 or a constant f) has the solution p = 0:
+ * p is set to 0 and hist holds the single entry 0, with no cycle.
  * Returns MG_ENOCONV / MG_EBREAKDOWN with p and hist valid when a solve stops early.
  */
 int mg_solve(mg_ctx* ctx, const double* f, double* p, int batch, double tol, int max_cycles,

@@ -53,6 +53,8 @@ int fail(int code, const char* fmt, ...) {
 
 constexpr double kPinvRtol = 1e-12;
 constexpr double kBreakdownGrowth = 1e3;
+// ||P f|| below this fraction of ||f|| is rounding left by the mean removal
+constexpr double kZeroRhs = 64.0 * 2.220446049250313e-16;
 
 // device scalar slots
 enum { S_FMEAN = 0, S_FNORM2 = 1, S_RNORM2 = 2, S_PMEAN = 3, S_DW = 4, S_DR = 5, S_ZW = 6, S_COUNT = 8 };
@@ -263,9 +265,11 @@ int solve_one(mg_ctx* c, const double* f, double* p, double tol, int max_cycles,
   MG_TRY(read_scalars(c, s, 3));
   *removed_mean = s[S_FMEAN];
   const double nf = std::sqrt(s[S_FNORM2]);
+  // ||f|| over the fluid cells from ||P f||^2 + (fluid cells) x mean^2, without a pass
+  const double nf_all = std::sqrt(s[S_FNORM2] + static_cast<double>(c->active) * s[S_FMEAN] * s[S_FMEAN]);
   int nh = 0;
   *cycles = 0;
-  if (!(nf > 0.0)) {   // P f = 0: the solution is p = 0
+  if (!(nf > kZeroRhs * nf_all)) {   // P f = 0 to rounding (f = 0, f constant): p = 0
     MG_HIP(hipMemsetAsync(p, 0, sizeof(double) * cells(a), c->stream));
     if (hist) hist[0] = 0.0;
     *n_hist = 1;

@@ -223,6 +223,33 @@ def test_errors_reported():
         MG(dev(np.ones((12,) * 3)), dev(np.ones((12,) * 3)), dev(np.ones((12,) * 3)), dev(np.ones((12,) * 3, np.uint8)))
 
 
+@pytest.mark.parametrize("mixed,krylov", [(False, False), (True, False), (False, True)])
+def test_degenerate_right_hand_sides(mixed, krylov):
+    """f = 0 and a constant f (whose projection is 0): the solution is p = 0 whatever the
+    guess, with the history [0] and no cycle; 64^3, so both finest-grid paths apply."""
+    from paper_1410_2240_amd import MG
+    inp, _ = workload("c5", 64)
+    mg = MG.from_rho(dev(inp.rho), dev(inp.mask), mixed=mixed, krylov=krylov)
+    guess = dev(np.random.default_rng(5).standard_normal(inp.f.shape))
+    for f in (np.zeros_like(inp.f), np.full_like(inp.f, 3.5)):
+        p, hist, st = mg.solve(dev(f), p=guess.clone(), tol=1e-10)
+        assert st["status"] == 0 and st["cycles"] == 0 and hist == [0.0]
+        assert not host(p).any()
+
+
+def test_no_fluid_rejected_at_setup():
+    """A grid with no fluid cell (all body), or one whose only fluid cell has no open
+    face, has no equation: setup reports MG_EINVAL."""
+    from paper_1410_2240_amd import MG, MGError
+    from paper_1410_2240_amd._lib import MG_EINVAL
+    N = 16
+    rho = dev(np.ones((N, N, N)))
+    for mask in (np.zeros((N, N, N), np.uint8), np.eye(1, N ** 3, 77, dtype=np.uint8).reshape(N, N, N)):
+        with pytest.raises(MGError) as ei:
+            MG.from_rho(rho, dev(mask))
+        assert ei.value.code == MG_EINVAL
+
+
 def test_incompatible_rhs_mean_removed():
     inp, H = workload("c2", 32)
     mg = mg_from_inputs(inp)
