@@ -205,13 +205,27 @@ def relres(p, fhat, lev: Level, nf: float) -> float:
     return float(np.sqrt(np.sum(r * r))) / nf
 
 
+# A projected right-hand side below this fraction of ||f|| (fluid cells) is rounding
+# left by the mean removal: P f = 0, whose solution is p = 0 (f = 0, f constant).
+ZERO_RHS = 64.0 * np.finfo(np.float64).eps
+
+
+def zero_range(f, fhat, mask) -> bool:
+    """True when P f is zero to rounding: ||P f|| <= ZERO_RHS ||f|| over the fluid cells."""
+    nf_all = float(np.sqrt(np.sum(np.where(mask, np.asarray(f, np.float64), 0.0) ** 2)))
+    return not float(np.sqrt(np.sum(fhat * fhat))) > ZERO_RHS * nf_all
+
+
 def solve(hier: Hierarchy, f, p0=None, tol: float = 1e-10, max_cycles: int = 100):
     """FP64 V-cycles until the relative residual reaches tol.
 
-    Returns (p, hist) with hist[0] the relative residual of the initial guess.
+    Returns (p, hist) with hist[0] the relative residual of the initial guess; a right-
+    hand side with no component in the range of A (zero_range) returns (0, [0]).
     """
     lev = hier.fine
     fhat = project(np.asarray(f, np.float64), lev.mask)
+    if zero_range(f, fhat, lev.mask):
+        return np.zeros_like(fhat), [0.0]
     nf = float(np.sqrt(np.sum(fhat * fhat)))
     p = np.zeros_like(fhat) if p0 is None else np.where(lev.mask, p0, 0.0)
     hist = [relres(p, fhat, lev, nf)]
@@ -284,6 +298,8 @@ def solve_fcg(hier: Hierarchy, f, p0=None, tol: float = 1e-10, max_iters: int = 
     """
     lev = hier.fine
     fhat = project(np.asarray(f, np.float64), lev.mask)
+    if zero_range(f, fhat, lev.mask):
+        return np.zeros_like(fhat), [0.0]
     nf = float(np.sqrt(np.sum(fhat * fhat)))
     p = np.zeros_like(fhat) if p0 is None else np.where(lev.mask, p0, 0.0)
     lv32 = fp32_levels(hier) if mixed else None

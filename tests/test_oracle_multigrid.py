@@ -348,3 +348,22 @@ def test_fp32_density_level_is_the_rounded_operator_within_float_ulps():
         ref = b64.astype(np.float32)
         ulp = np.spacing(np.maximum(ref, np.float32(1e-30)))
         assert np.max(np.abs(b32.astype(np.float64) - ref) / ulp) <= 2.0
+
+
+def test_rhs_without_range_component_gives_zero():
+    """Reading C21: f = 0 and a constant f project to zero (to rounding), so both
+    solvers return p = 0 with the history [0] whatever the guess; an ordinary right-hand
+    side is unaffected (history starts at 1 from p = 0)."""
+    import oracle.multigrid as omg
+    H = random_hierarchy(16, 41, body=True, contrast=1000.0)
+    g = np.random.default_rng(42)
+    guess = g.standard_normal((16, 16, 16))
+    for f in (np.zeros((16, 16, 16)), np.full((16, 16, 16), 0.1)):
+        assert omg.zero_range(f, project(f, H.fine.mask), H.fine.mask)
+        for solver in (omg.solve, omg.solve_fcg):
+            p, hist = solver(H, f, p0=guess)
+            assert hist == [0.0] and not p.any()
+    f = g.standard_normal((16, 16, 16))
+    assert not omg.zero_range(f, project(f, H.fine.mask), H.fine.mask)
+    _, hist = omg.solve(H, f, tol=1e-8)
+    assert hist[0] == 1.0 and hist[-1] <= 1e-8
