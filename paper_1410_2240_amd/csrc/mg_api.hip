@@ -90,6 +90,7 @@ struct mg_ctx {
   long long* counters = nullptr;
   double *kr = nullptr, *kz = nullptr, *kd = nullptr, *kw = nullptr;   // flexible-CG vectors
   double* host = nullptr;   // pinned, S_COUNT doubles
+  hipEvent_t read_done = nullptr;   // the last read-back of scalars has landed in host
   long long active = 0, dropped = 0;
 
   View<double> v64(int l) const {
@@ -124,15 +125,17 @@ long long cells(const Level& a) { return static_cast<long long>(a.n) * a.n * a.n
 // sweep, which alternates p with the level's second buffer; an odd count ends with a
 // copy back.  Small grids use two in-place half-sweeps per sweep.  zero_in: p is known to
 // be zero, so the first one-pass sweep does not read it (p's memory may then hold
-// anything; half-sweep grids still need it zeroed).
+// anything; half-sweep grids still need it zeroed).  first_done: the first sweep
+// (p -> second buffer) has already been queued (see first_sweep), so start from its output.
 template <typename T>
-int smooth(mg_ctx* c, int l, T* p, const T* f, const double* fshift, int sweeps, int order, bool zero_in = false) {
+int smooth(mg_ctx* c, int l, T* p, const T* f, const double* fshift, int sweeps, int order, bool zero_in = false,
+           bool first_done = false) {
   const Level& a = c->lv[l];
   const View<T> v = c->view<T>(l);
   if (mg::fused_sweep_supported(a.q)) {
-    T* src = p;
-    T* dst = v.t;
-    for (int s = 0; s < sweeps; ++s) {
+    T* src = first_done ? v.t : p;
+    T* dst = first_done ? p : v.t;
+    for (int s = first_done ? 1 : 0; s < sweeps; ++s) {
       MG_HIP(mg::launch_rbgs_fused<T>(src, dst, f, v.bx, v.by, v.bz, v.rt, a.q, a.h, order, fshift,
                                       zero_in && s == 0, c->stream));
       T* tmp = src;
@@ -163,9 +166,21 @@ int residual_restrict(mg_ctx* c, int l, const T* p, const T* f, const double* fs
   return MG_OK;
 }
 
-// zero_in: p enters as zero (a correction), see smooth()
+// The first pre-smoothing sweep of a finest-grid cycle on a one-pass-swept grid: it
+// writes only the grid's second buffer (p is read, or not at all with zero_in), so it can
+// be queued before the host has read the convergence check, and the cycle then starts
+// from its output (vcycle with first_done); if the check ends the solve, it is discarded.
 template <typename T>
-int vcycle(mg_ctx* c, int l, T* p, const T* f, const double* fshift, bool zero_in = false) {
+int first_sweep(mg_ctx* c, T* p, const T* f, const double* fshift, bool zero_in) {
+  const Level& a = c->lv[0];
+  const View<T> v = c->view<T>(0);
+  MG_HIP(mg::launch_rbgs_fused<T>(p, v.t, f, v.bx, v.by, v.bz, v.rt, a.q, a.h, MG_PRE, fshift, zero_in, c->stream));
+  return MG_OK;
+}
+
+// zero_in: p enters as zero (a correction), see smooth(); first_done: see first_sweep()
+template <typename T>
+int vcycle(mg_ctx* c, int l, T* p, const T* f, const double* fshift, bool zero_in = false, bool first_done = false) {
   if (c->lv[l].n <= mg::kCoarseCycleMaxN) {
     // grids of 16^3 and below: the rest of the cycle in one single-workgroup launch
     mg::CoarseCycle<T> a{};
@@ -189,7 +204,7 @@ int vcycle(mg_ctx* c, int l, T* p, const T* f, const double* fshift, bool zero_i
     return MG_OK;
   }
   const View<T> next = c->view<T>(l + 1);
-  MG_TRY(smooth<T>(c, l, p, f, fshift, 2, MG_PRE, zero_in));
+  MG_TRY(smooth<T>(c, l, p, f, fshift, 2, MG_PRE, zero_in, first_done));
   MG_TRY(residual_restrict<T>(c, l, p, f, fshift, next.f, next.e));
   MG_TRY(vcycle<T>(c, l + 1, next.e, next.f, nullptr, true));   // restriction zeroed next.e
   MG_HIP(mg::launch_prolong_add<T>(next.e, p, c->lv[l].mask, c->lv[l].q, c->stream));
@@ -204,11 +219,22 @@ int reduce(mg_ctx* c, int nparts, double scale, int slot) {
   return MG_OK;
 }
 
-int read_scalars(mg_ctx* c, double* out, int count) {
+// Read-backs in two halves: work queued between them runs while the host waits.
+int issue_scalars(mg_ctx* c, int count) {
   MG_HIP(hipMemcpyAsync(c->host, c->scal, sizeof(double) * count, hipMemcpyDeviceToHost, c->stream));
-  MG_HIP(hipStreamSynchronize(c->stream));
+  MG_HIP(hipEventRecord(c->read_done, c->stream));
+  return MG_OK;
+}
+
+int wait_scalars(mg_ctx* c, double* out, int count) {
+  MG_HIP(hipEventSynchronize(c->read_done));
   std::memcpy(out, c->host, sizeof(double) * count);
   return MG_OK;
+}
+
+int read_scalars(mg_ctx* c, double* out, int count) {
+  MG_TRY(issue_scalars(c, count));
+  return wait_scalars(c, out, count);
 }
 
 // ||r||^2 of the finest residual into scal[S_RNORM2]; optional FP32 copy of r (with
@@ -261,8 +287,22 @@ int solve_one(mg_ctx* c, const double* f, double* p, double tol, int max_cycles,
   const bool zin = mg::fused_sweep_supported(a.q);
   float* e32_zero = zin ? nullptr : e32;
   MG_TRY(residual_norm(c, p, f, fshift, r32, e32_zero));
+  // The next cycle's first finest-grid sweep is queued before each convergence check is
+  // read back (first_sweep), so the GPU does not idle while the host decides.
+  const bool spec = mg::fused_sweep_supported(a.q) && a.n > mg::kCoarseCycleMaxN;
+  const bool krylov = (c->flags & MG_KRYLOV) != 0;
+  auto cycle_first_sweep = [&]() -> int {
+    if (mixed) return first_sweep<float>(c, e32, r32, nullptr, true);
+    return first_sweep<double>(c, p, f, fshift, false);
+  };
+  bool ahead = false;   // the next cycle's first sweep is queued
   double s[3];
-  MG_TRY(read_scalars(c, s, 3));
+  MG_TRY(issue_scalars(c, 3));
+  if (spec && !krylov && max_cycles > 0) {
+    MG_TRY(cycle_first_sweep());
+    ahead = true;
+  }
+  MG_TRY(wait_scalars(c, s, 3));
   *removed_mean = s[S_FMEAN];
   const double nf = std::sqrt(s[S_FNORM2]);
   // ||f|| over the fluid cells from ||P f||^2 + (fluid cells) x mean^2, without a pass
@@ -287,15 +327,19 @@ int solve_one(mg_ctx* c, const double* f, double* p, double tol, int max_cycles,
     const int q = a.q;
     const float* z32 = mixed ? e32 : nullptr;
     const double* z64 = mixed ? nullptr : kz;
-    auto precondition = [&]() -> int {
-      if (mixed) return vcycle<float>(c, 0, e32, r32, nullptr, true);
-      return vcycle<double>(c, 0, kz, kr, nullptr, true);
+    auto precondition = [&](bool first_done) -> int {
+      if (mixed) return vcycle<float>(c, 0, e32, r32, nullptr, true, first_done);
+      return vcycle<double>(c, 0, kz, kr, nullptr, true, first_done);
+    };
+    auto precondition_first_sweep = [&]() -> int {
+      if (mixed) return first_sweep<float>(c, e32, r32, nullptr, true);
+      return first_sweep<double>(c, kz, kr, nullptr, true);
     };
     double* kz_zero = (mixed || zin) ? nullptr : kz;
     if (std::isfinite(r) && r > tol && max_cycles > 0) {
       // the first residual pass also wrote r (and zeroed the preconditioner output)
       MG_TRY(residual_norm(c, p, f, fshift, r32, e32_zero, kr, kz_zero));
-      MG_TRY(precondition());
+      MG_TRY(precondition(false));
       MG_HIP(mg::launch_fcg_dir(z64, z32, kd, nullptr, nullptr, q, c->stream));
     }
     while (std::isfinite(r) && r > tol && *cycles < max_cycles) {
@@ -313,7 +357,10 @@ int solve_one(mg_ctx* c, const double* f, double* p, double tol, int max_cycles,
       MG_TRY(reduce_set(c, 2, nb, S_RNORM2));
       ++*cycles;
       double sn[8];
-      MG_TRY(read_scalars(c, sn, 8));
+      MG_TRY(issue_scalars(c, 8));
+      ahead = spec && *cycles < max_cycles;
+      if (ahead) MG_TRY(precondition_first_sweep());
+      MG_TRY(wait_scalars(c, sn, 8));
       r = std::sqrt(sn[S_RNORM2]) / nf;
       if (hist) hist[nh] = r;
       ++nh;
@@ -323,7 +370,7 @@ int solve_one(mg_ctx* c, const double* f, double* p, double tol, int max_cycles,
         break;
       }
       if (r <= tol || *cycles >= max_cycles) break;
-      MG_TRY(precondition());
+      MG_TRY(precondition(ahead));
       MG_HIP(mg::launch_fcg_zw(z64, z32, kw, q, part(c, 3), &nb, c->stream));
       MG_TRY(reduce_set(c, 3, nb, S_ZW));
       MG_HIP(mg::launch_fcg_dir(z64, z32, kd, c->scal + S_ZW, c->scal + S_DW, q, c->stream));
@@ -338,7 +385,7 @@ int solve_one(mg_ctx* c, const double* f, double* p, double tol, int max_cycles,
   while (!(c->flags & MG_KRYLOV) && std::isfinite(r) && r > tol && *cycles < max_cycles) {
     if (mixed) {
       // FP32 V-cycle for the correction from the FP32 copy of the FP64 residual, FP64 update
-      MG_TRY(vcycle<float>(c, 0, e32, r32, nullptr, true));
+      MG_TRY(vcycle<float>(c, 0, e32, r32, nullptr, true, ahead));
       if (fuse_update) {
         double* next = cur == p ? a.t : p;
         int nbu = 0;
@@ -351,12 +398,15 @@ int solve_one(mg_ctx* c, const double* f, double* p, double tol, int max_cycles,
         MG_TRY(residual_norm(c, p, f, fshift, r32, e32_zero));
       }
     } else {
-      MG_TRY(vcycle<double>(c, 0, p, f, fshift));
+      MG_TRY(vcycle<double>(c, 0, p, f, fshift, false, ahead));
       MG_TRY(residual_norm(c, p, f, fshift, r32, e32_zero));
     }
     ++*cycles;
     double sn[3];
-    MG_TRY(read_scalars(c, sn, 3));
+    MG_TRY(issue_scalars(c, 3));
+    ahead = spec && *cycles < max_cycles;
+    if (ahead) MG_TRY(cycle_first_sweep());
+    MG_TRY(wait_scalars(c, sn, 3));
     r = std::sqrt(sn[S_RNORM2]) / nf;
     if (hist) hist[nh] = r;
     ++nh;
@@ -505,6 +555,10 @@ int setup_impl(mg_ctx** out, void* workspace, size_t ws_bytes, const double* bx,
       hipSuccess) {
     c->host = nullptr;
     return cleanup(fail(MG_EHIP, "hipHostMalloc of the read-back buffer failed"));
+  }
+  if (hipEventCreateWithFlags(&c->read_done, hipEventDisableTiming) != hipSuccess) {
+    c->read_done = nullptr;
+    return cleanup(fail(MG_EHIP, "hipEventCreateWithFlags of the read-back event failed"));
   }
   hipStream_t s = c->stream;
   int rc = MG_OK;
@@ -766,6 +820,7 @@ int mg_project(mg_ctx* ctx, double* ux, double* uy, double* uz, const double* rx
 void mg_destroy(mg_ctx* ctx) {
   if (!ctx) return;
   if (ctx->host) (void)hipHostFree(ctx->host);
+  if (ctx->read_done) (void)hipEventDestroy(ctx->read_done);
   delete ctx;
 }
 
