@@ -555,8 +555,16 @@ __global__ __launch_bounds__(TX / 2 * TY) void k_rbgs_fused(const T* __restrict_
       gs<T, W>(L[s0], rt_, c, ODD1 ? below1 : below0, at<T, W>(L[s1], rt_, c), get_black(), h2, fs);
       below0 = at<T, W>(L[s0], rt_, ct);
       below1 = at<T, W>(L[s0], rt_, ct + 1);
-      *reinterpret_cast<V2*>(reinterpret_cast<char*>(pout + (static_cast<long long>(k) << (2 * q))) + po.c) =
-          V2{below0, below1};
+      char* out = reinterpret_cast<char*>(pout + (static_cast<long long>(k) << (2 * q))) + po.c;
+      if constexpr (sizeof(T) == 8) {
+        // FP64: a streaming store (the plane out is read by the next pass, not this one);
+        // it leaves the cache lines this sweep re-reads in place
+        typedef T NV __attribute__((ext_vector_type(2)));
+        const NV v = {below0, below1};
+        __builtin_nontemporal_store(v, reinterpret_cast<NV*>(out));
+      } else {
+        *reinterpret_cast<V2*>(out) = V2{below0, below1};
+      }
     }
     put_black(black_next);
     if constexpr (RHO) {

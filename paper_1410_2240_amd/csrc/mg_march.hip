@@ -91,6 +91,13 @@ __device__ __forceinline__ void pair_r(const PF<T>& F, V2 pc, T pl, T pr, V2 pyd
   r1 = D1 > T(0) ? fmad(-inv_h2, s1, fv.y - fs) : T(0);
 }
 
+// a 16-byte store that does not keep its lines in the caches
+__device__ __forceinline__ void stream_store(double* dst, double2 v) {
+  typedef double NV __attribute__((ext_vector_type(2)));
+  const NV x = {v.x, v.y};
+  __builtin_nontemporal_store(x, reinterpret_cast<NV*>(dst));
+}
+
 // p + e on active cells (density finite); the update of a mixed-precision refinement step
 __device__ __forceinline__ double add_active(double p, float e, double rt) {
   return rt < __builtin_huge_val() ? p + static_cast<double>(e) : p;
@@ -254,9 +261,9 @@ __global__ __launch_bounds__(kMarchThreads) void k_residual_march(MarchArgs<T> a
     const long long plane = static_cast<long long>(k) << (2 * q);
     const long long ca = plane + oa / sizeof(T), cb = plane + ob / sizeof(T);
     if constexpr (NORM) {
-      if constexpr (UPD) {
-        *reinterpret_cast<double2*>(a.pout + ca) = pa;
-        *reinterpret_cast<double2*>(a.pout + cb) = pb;
+      if constexpr (UPD) {   // read again only after the next FP32 cycle: streaming stores
+        stream_store(a.pout + ca, pa);
+        stream_store(a.pout + cb, pb);
       }
       acc = fmad(r1a, r1a, fmad(r0a, r0a, acc));
       acc = fmad(r1b, r1b, fmad(r0b, r0b, acc));
@@ -291,8 +298,8 @@ __global__ __launch_bounds__(kMarchThreads) void k_residual_march(MarchArgs<T> a
     } else {
       // the residual of f = 0 is -A d
       const double2 wa{-r0a, -r1a}, wb{-r0b, -r1b};
-      *reinterpret_cast<double2*>(a.w + ca) = wa;
-      *reinterpret_cast<double2*>(a.w + cb) = wb;
+      stream_store(a.w + ca, wa);   // read again only by the update pass
+      stream_store(a.w + cb, wb);
       const double2 rva = ld2(plane_rsrc(a.r, k, q), oa, 0.0), rvb = ld2(plane_rsrc(a.r, k, q), ob, 0.0);
       acc = fmad(pa.y, wa.y, fmad(pa.x, wa.x, acc));
       acc = fmad(pb.y, wb.y, fmad(pb.x, wb.x, acc));
