@@ -623,10 +623,77 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle(CoarseCycle<T> 
     f[0][c] = a.f[0][c];
   }
   __syncthreads();
+  // FP32: the face coefficients of the cells this thread updates on the two grids that
+  // are smoothed, loaded once: every half-sweep would otherwise wait for them from L2
+  // again, one pair after another.  Pair slot u of grid l is pair tid + u x 512 (at most
+  // 4 on a 16^3 grid), colour 0 / 1 its red / black cell.  (FP64 reads them from L2 in
+  // each half-sweep: held in registers they would spill.)
+  constexpr bool PRE = sizeof(T) == 4;
+  constexpr int U0 = (kCoarseCycleMaxN * kCoarseCycleMaxN * kCoarseCycleMaxN / 2) / kCoarseThreads;
+  struct CF {
+    T xm, xp, ym, yp, zm, zp;
+  };
+  CF cf0[U0][2], cf1[2];
+  auto pair_cell = [&](int l, int pr, int colour, int& i, int& j, int& k) {
+    const int q = a.q[l], m = (1 << q) - 1;
+    const int ip = pr & (m >> 1);
+    j = (pr >> (q - 1)) & m;
+    k = pr >> (2 * q - 1);
+    i = 2 * ip + ((colour + j + k) & 1);
+  };
+  auto load_cf = [&](int l, int pr, int colour) {
+    int i, j, k;
+    pair_cell(l, pr, colour, i, j, k);
+    const Faces<T> F = load_faces(a.bx[l], a.by[l], a.bz[l], i, j, k, a.q[l]);
+    return CF{F.xm, F.xp, F.ym, F.yp, F.zm, F.zp};
+  };
+  auto preload0 = [&]() {
+    if constexpr (!PRE) return;
+#pragma unroll
+    for (int u = 0; u < U0; ++u) {
+      const int pr = tid + u * kCoarseThreads;
+      if (last > 0 && pr < (1 << (3 * a.q[0] - 1))) {
+        cf0[u][0] = load_cf(0, pr, 0);
+        cf0[u][1] = load_cf(0, pr, 1);
+      }
+    }
+  };
+  preload0();
+  if (PRE && last > 1 && tid < (1 << (3 * a.q[1] - 1))) {
+    cf1[0] = load_cf(1, tid, 0);
+    cf1[1] = load_cf(1, tid, 1);
+  }
+  // the update of gs_pair with preloaded coefficients (same operations, same order)
+  auto gs_pre = [&](int l, int pr, int colour, const CF& C, T fs) {
+    const int q = a.q[l], n = 1 << q, m = n - 1;
+    int i, j, k;
+    pair_cell(l, pr, colour, i, j, k);
+    const int c = cell(i, j, k, q);
+    const int cxm = cell((i - 1) & m, j, k, q), cxp = cell((i + 1) & m, j, k, q);
+    const int cym = cell(i, (j - 1) & m, k, q), cyp = cell(i, (j + 1) & m, k, q);
+    const int czm = k > 0 ? c - (1 << (2 * q)) : c, czp = k < m ? c + (1 << (2 * q)) : c;
+    T* p = e[l];
+    const T pxm = p[cxm], pxp = p[cxp], pym = p[cym], pyp = p[cyp], pzm = p[czm], pzp = p[czp];
+    const T fc = f[l][c];
+    const T D = C.xm + C.xp + C.ym + C.yp + C.zm + C.zp;
+    if (!(D > T(0))) return;
+    const T S = C.xm * pxm + C.xp * pxp + C.ym * pym + C.yp * pyp + C.zm * pzm + C.zp * pzp;
+    p[c] = (S - a.h2[l] * (fc - fs)) / D;
+  };
   auto sweep = [&](int l, int colour, const T* bx, const T* by, const T* bz) {
     const T fs = (l == 0 && a.fshift) ? static_cast<T>(*a.fshift) : T(0);
-    for (int pr = tid; pr < (1 << (3 * a.q[l] - 1)); pr += kCoarseThreads)
-      gs_pair(e[l], f[l], bx, by, bz, a.q[l], a.h2[l], colour, fs, pr);
+    if constexpr (!PRE) {
+      for (int pr = tid; pr < (1 << (3 * a.q[l] - 1)); pr += kCoarseThreads)
+        gs_pair(e[l], f[l], bx, by, bz, a.q[l], a.h2[l], colour, fs, pr);
+    } else if (l == 0) {
+#pragma unroll
+      for (int u = 0; u < U0; ++u) {
+        const int pr = tid + u * kCoarseThreads;
+        if (pr < (1 << (3 * a.q[0] - 1))) gs_pre(0, pr, colour, cf0[u][colour], fs);
+      }
+    } else if (tid < (1 << (3 * a.q[1] - 1))) {
+      gs_pre(1, tid, colour, cf1[colour], fs);
+    }
     __syncthreads();
   };
 #pragma unroll
@@ -649,6 +716,9 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle(CoarseCycle<T> 
 #pragma unroll
   for (int l = 1; l >= 0; --l) {
     if (l < last) {
+      // the first grid's coefficients again for its post-smoothing (not kept in
+      // registers through the coarser grids), in flight during the prolongation
+      if (l == 0) preload0();
       for (int C = tid; C < (1 << (3 * (a.q[l] - 1))); C += kCoarseThreads)
         prolong_cell(e[l + 1], e[l], a.mask[l], a.q[l], C);
       __syncthreads();
