@@ -98,7 +98,7 @@ def test_mixed_density_form_converges_to_the_same_solution(krylov):
     assert relerr(host(pa), host(pb)) <= 1e-9
 
 
-@pytest.mark.parametrize("N", [64, 128])
+@pytest.mark.parametrize("N", [64, 128, 256])
 @pytest.mark.parametrize("order", [0, 1])
 def test_fp32_density_sweep_matches_emulation(N, order):
     """The FP32 density-form sweep against the oracle's float32 Gauss-Seidel on the
