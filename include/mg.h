@@ -157,6 +157,34 @@ int mg_set_stream(mg_ctx* ctx, void* hip_stream);
 int mg_solve(mg_ctx* ctx, const double* f, double* p, int batch, double tol, int max_cycles,
              double* hist, int* n_hist, mg_stats* stats);
 
+/*
+ * Concurrent right-hand sides of one hierarchy, e.g. the batch of adjoint solves of a
+ * differentiated projection (A mu_b = P w_b, every b on the same operator).  Small
+ * grids leave most of the GPU idle in each launch, so solving several right-hand
+ * sides at once on separate streams raises throughput; the results are bit for bit
+ * those of solving them one after another.
+ *
+ * mg_lane_workspace_size: bytes of one lane's scratch (the arrays a solve writes:
+ * right-hand sides, corrections and second buffers of every grid, the flexible-CG
+ * vectors, reduction partials and scalars) for these dims and flags; 0 if unsupported.
+ *
+ * mg_add_lanes: gives ctx `lanes` extra lanes (1 <= lanes <= MG_MAX_LANES, once per
+ * context).  workspace: DEVICE memory of at least lanes x mg_lane_workspace_size bytes,
+ * 256-byte aligned, owned by the caller and outliving ctx; lane w uses the w-th slice.
+ * Each lane gets a non-blocking HIP stream of default priority (created on the current
+ * device, destroyed by mg_destroy), a pinned read-back buffer and two events; no device
+ * memory is allocated.  From then on mg_solve with batch > 1 solves up to 1 + lanes
+ * items at a time: item b on lane b mod (1 + lanes), lane 0 being ctx on its own stream,
+ * each extra lane driven by a host thread of its own.  The lane streams start after the
+ * work already queued on ctx's stream, and ctx's stream waits for all of them before
+ * anything queued after mg_solve.  Errors: MG_EINVAL (null ctx, lanes out of range, lanes
+ * already added), MG_EWORKSPACE (workspace null, misaligned or too small), MG_EHIP.  On
+ * error no lane is added.
+ */
+#define MG_MAX_LANES 16
+size_t mg_lane_workspace_size(const int dims[3], int flags);
+int mg_add_lanes(mg_ctx* ctx, void* workspace, size_t ws_bytes, int lanes);
+
 /* Ap_b = A p_b on the finest grid (0 in the body). */
 int mg_apply(mg_ctx* ctx, const double* p, double* Ap, int batch);
 

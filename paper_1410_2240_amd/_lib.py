@@ -15,6 +15,7 @@ MG_OK, MG_EINVAL, MG_EWORKSPACE, MG_EHIP, MG_ENOCONV, MG_EBREAKDOWN = 0, -1, -2,
 MG_FP64, MG_MIXED, MG_KRYLOV, MG_COARSEN_DENSITY = 0, 1, 2, 4
 MG_PREC_F64, MG_PREC_F32 = 0, 1
 MG_PRE, MG_POST = 0, 1
+MG_MAX_LANES = 16
 
 ERROR_NAMES = {MG_EINVAL: "MG_EINVAL", MG_EWORKSPACE: "MG_EWORKSPACE", MG_EHIP: "MG_EHIP",
                MG_ENOCONV: "MG_ENOCONV", MG_EBREAKDOWN: "MG_EBREAKDOWN"}
@@ -43,6 +44,8 @@ SIGNATURES = {
     "mg_setup_from_rho": (_I, [ctypes.POINTER(_P), _P, ctypes.c_size_t, _P, _P, _DIMS, _D, _I, _P]),
     "mg_set_stream": (_I, [_P, _P]),
     "mg_solve": (_I, [_P, _P, _P, _I, _D, _I, ctypes.POINTER(_D), ctypes.POINTER(_I), ctypes.POINTER(MgStats)]),
+    "mg_lane_workspace_size": (ctypes.c_size_t, [_DIMS, _I]),
+    "mg_add_lanes": (_I, [_P, _P, ctypes.c_size_t, _I]),
     "mg_apply": (_I, [_P, _P, _P, _I]),
     "mg_coeff_grad": (_I, [_P, _P, _P, _I, _P, _P, _P, _P]),
     "mg_divergence": (_I, [_P, _P, _P, _P, _P, _P, _P, _D, _P]),

@@ -6,12 +6,14 @@
 // object is a small pinned buffer for those read-backs.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <type_traits>
 #include <vector>
 
@@ -92,6 +94,13 @@ struct mg_ctx {
   double* host = nullptr;   // pinned, S_COUNT doubles
   hipEvent_t read_done = nullptr;   // the last read-back of scalars has landed in host
   long long active = 0, dropped = 0;
+  // Concurrent right-hand sides (mg_add_lanes): each lane is a context of its own that
+  // shares this one's coefficients, masks and pseudo-inverse and owns its scratch, a
+  // stream the library created, a read-back buffer and events.
+  std::vector<mg_ctx*> lanes;
+  bool own_stream = false;              // a lane: `stream` was created by the library
+  hipEvent_t order_event = nullptr;     // joins this context's stream with the caller's
+  int device = 0;                       // a lane: the device its stream belongs to
 
   View<double> v64(int l) const {
     const Level& a = lv[l];
@@ -650,6 +659,106 @@ int setup_impl(mg_ctx** out, void* workspace, size_t ws_bytes, const double* bx,
   return MG_OK;
 }
 
+// One lane: a copy of ctx whose per-solve arrays live in `ws` (laid out by
+// build_lane_plan) and whose work runs on a new non-blocking stream of `device`.
+int make_lane(mg_ctx* ctx, unsigned char* ws, const mg::Plan& lp, int device, mg_ctx** out) {
+  mg_ctx* c = new mg_ctx(*ctx);
+  c->lanes.clear();
+  c->host = nullptr;
+  c->read_done = nullptr;
+  c->order_event = nullptr;
+  c->stream = nullptr;
+  c->own_stream = false;
+  c->device = device;
+  for (int l = 0; l < c->L; ++l) {
+    Level& a = c->lv[l];
+    const mg::LevelPlan& p = lp.lv[l];
+    a.f = at<double>(ws, p.f);
+    a.e = at<double>(ws, p.e);
+    a.t = at<double>(ws, p.t);
+    a.f32 = at<float>(ws, p.f32);
+    a.e32 = at<float>(ws, p.e32);
+    a.t32 = at<float>(ws, p.t32);
+  }
+  c->partials = at<double>(ws, lp.partials);
+  c->scal = at<double>(ws, lp.scalars);
+  c->kr = at<double>(ws, lp.kr);
+  c->kz = at<double>(ws, lp.kz);
+  c->kd = at<double>(ws, lp.kd);
+  c->kw = at<double>(ws, lp.kw);
+  *out = c;
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->host), sizeof(double) * S_COUNT, hipHostMallocDefault) != hipSuccess) {
+    c->host = nullptr;
+    return fail(MG_EHIP, "hipHostMalloc of a lane's read-back buffer failed");
+  }
+  if (hipEventCreateWithFlags(&c->read_done, hipEventDisableTiming) != hipSuccess) {
+    c->read_done = nullptr;
+    return fail(MG_EHIP, "hipEventCreateWithFlags of a lane's read-back event failed");
+  }
+  if (hipEventCreateWithFlags(&c->order_event, hipEventDisableTiming) != hipSuccess) {
+    c->order_event = nullptr;
+    return fail(MG_EHIP, "hipEventCreateWithFlags of a lane's order event failed");
+  }
+  // non-blocking: no implicit ordering against the default stream, on which the caller
+  // (and the context's own lane) may run; default priority
+  hipStream_t s = nullptr;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return fail(MG_EHIP, "hipStreamCreate failed");
+  c->stream = s;
+  c->own_stream = true;
+  return MG_OK;
+}
+
+struct LaneResult {
+  int rc = MG_OK, nh = 0, cyc = 0;
+  double rm = 0.0, fr = 0.0;
+  std::string err;
+};
+
+// Right-hand side b of a batch on lane w of W (lane 0 = the context itself on the
+// caller's stream) runs solve_one unchanged, so each result is bit for bit that of the
+// one-at-a-time loop.  A lane stops after an argument or HIP error, as that loop does.
+void run_lane(mg_ctx* c, int w, int W, const double* f, double* p, int batch, long long n3, double tol,
+              int max_cycles, double* hist, std::vector<LaneResult>* res) {
+  if (w > 0 && hipSetDevice(c->device) != hipSuccess) {
+    for (int b = w; b < batch; b += W) {
+      (*res)[b].rc = MG_EHIP;
+      (*res)[b].err = "hipSetDevice in a lane thread failed";
+    }
+    return;
+  }
+  for (int b = w; b < batch; b += W) {
+    LaneResult& o = (*res)[b];
+    double* hb = hist ? hist + static_cast<long long>(b) * (max_cycles + 1) : nullptr;
+    o.rc = solve_one(c, f + b * n3, p + b * n3, tol, max_cycles, hb, &o.nh, &o.rm, &o.fr, &o.cyc);
+    if (o.rc != MG_OK) o.err = g_error;
+    if (o.rc == MG_EINVAL || o.rc == MG_EHIP) break;
+  }
+}
+
+// mg_solve over lanes: the lane streams start after the caller's earlier work, one host
+// thread per extra lane drives its share of the batch, and the caller's stream waits for
+// every lane's last work before anything queued after this call.
+int solve_lanes(mg_ctx* ctx, const double* f, double* p, int batch, double tol, int max_cycles, double* hist,
+                std::vector<LaneResult>& res) {
+  const int W = std::min(static_cast<int>(ctx->lanes.size()) + 1, batch);
+  const long long n3 = cells(ctx->lv[0]);
+  MG_HIP(hipEventRecord(ctx->order_event, ctx->stream));
+  for (int w = 1; w < W; ++w) MG_HIP(hipStreamWaitEvent(ctx->lanes[w - 1]->stream, ctx->order_event, 0));
+  std::vector<std::thread> threads;
+  threads.reserve(W - 1);
+  for (int w = 1; w < W; ++w)
+    threads.emplace_back(run_lane, ctx->lanes[w - 1], w, W, f, p, batch, n3, tol, max_cycles, hist, &res);
+  run_lane(ctx, 0, W, f, p, batch, n3, tol, max_cycles, hist, &res);
+  for (auto& t : threads) t.join();
+  int rc = MG_OK;
+  for (int w = 1; w < W; ++w) {
+    mg_ctx* lane = ctx->lanes[w - 1];
+    hipError_t e = hipEventRecord(lane->order_event, lane->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(ctx->stream, lane->order_event, 0);
+    if (e != hipSuccess && rc == MG_OK) rc = fail(MG_EHIP, "joining lane %d: %s", w, hipGetErrorString(e));
+  }
+  return rc;
+}
 
 }  // namespace
 
@@ -749,21 +858,32 @@ int mg_solve(mg_ctx* ctx, const double* f, double* p, int batch, double tol, int
   if (batch < 1) return fail(MG_EINVAL, "batch must be >= 1");
   if (!(tol > 0.0) || !std::isfinite(tol)) return fail(MG_EINVAL, "tol must be positive and finite");
   if (max_cycles < 0) return fail(MG_EINVAL, "max_cycles must be >= 0");
-  const long long n3 = cells(ctx->lv[0]);
-  int status = MG_OK, total_cycles = 0;
+  std::vector<LaneResult> res(batch);
+  if (!ctx->lanes.empty() && batch > 1) {
+    MG_TRY(solve_lanes(ctx, f, p, batch, tol, max_cycles, hist, res));
+  } else {
+    run_lane(ctx, 0, 1, f, p, batch, cells(ctx->lv[0]), tol, max_cycles, hist, &res);
+  }
+  // outcomes in batch order: the first argument or HIP error ends the call; otherwise
+  // the status and message of the first item that did not converge
+  int status = MG_OK, total_cycles = 0, first_bad = -1;
   double removed = 0.0, worst = 0.0;
   for (int b = 0; b < batch; ++b) {
-    int nh = 0, cyc = 0;
-    double rm = 0.0, fr = 0.0;
-    double* hb = hist ? hist + static_cast<long long>(b) * (max_cycles + 1) : nullptr;
-    const int rc = solve_one(ctx, f + b * n3, p + b * n3, tol, max_cycles, hb, &nh, &rm, &fr, &cyc);
-    if (n_hist) n_hist[b] = nh;
-    total_cycles += cyc;
-    removed = rm;
-    worst = std::fmax(worst, fr);
-    if (rc == MG_EINVAL || rc == MG_EHIP) return rc;
-    if (rc != MG_OK && status == MG_OK) status = rc;
+    const LaneResult& o = res[b];
+    if (n_hist) n_hist[b] = o.nh;
+    total_cycles += o.cyc;
+    removed = o.rm;
+    worst = std::fmax(worst, o.fr);
+    if (o.rc == MG_EINVAL || o.rc == MG_EHIP) {
+      g_error = o.err;
+      return o.rc;
+    }
+    if (o.rc != MG_OK && status == MG_OK) {
+      status = o.rc;
+      first_bad = b;
+    }
   }
+  if (first_bad >= 0) g_error = res[first_bad].err;
   if (stats) {
     stats->cycles = total_cycles;
     stats->levels = ctx->L;
@@ -819,9 +939,54 @@ int mg_project(mg_ctx* ctx, double* ux, double* uy, double* uz, const double* rx
 
 void mg_destroy(mg_ctx* ctx) {
   if (!ctx) return;
+  for (mg_ctx* lane : ctx->lanes) mg_destroy(lane);
+  if (ctx->own_stream && ctx->stream) {
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipStreamDestroy(ctx->stream);
+  }
   if (ctx->host) (void)hipHostFree(ctx->host);
   if (ctx->read_done) (void)hipEventDestroy(ctx->read_done);
+  if (ctx->order_event) (void)hipEventDestroy(ctx->order_event);
   delete ctx;
+}
+
+size_t mg_lane_workspace_size(const int dims[3], int flags) {
+  int n = 0;
+  mg::Plan plan;
+  if (mg::validate_dims(dims, &n) != 0 || mg::build_lane_plan(n, flags, &plan) != 0) return 0;
+  return plan.total;
+}
+
+int mg_add_lanes(mg_ctx* ctx, void* workspace, size_t ws_bytes, int lanes) {
+  if (!ctx) return fail(MG_EINVAL, "null context");
+  if (ctx->own_stream) return fail(MG_EINVAL, "a lane cannot have lanes");
+  if (!ctx->lanes.empty()) return fail(MG_EINVAL, "this context already has %zu lanes", ctx->lanes.size());
+  if (lanes < 1 || lanes > MG_MAX_LANES) return fail(MG_EINVAL, "lanes must be in [1, %d] (got %d)", MG_MAX_LANES, lanes);
+  mg::Plan lp;
+  if (mg::build_lane_plan(ctx->lv[0].n, ctx->flags, &lp) != 0) return fail(MG_EINVAL, "unsupported grid");
+  if (!workspace) return fail(MG_EWORKSPACE, "null workspace");
+  if (reinterpret_cast<uintptr_t>(workspace) % mg::kAlign != 0) return fail(MG_EWORKSPACE, "workspace not 256-byte aligned");
+  if (ws_bytes / lp.total < static_cast<size_t>(lanes))
+    return fail(MG_EWORKSPACE, "workspace %zu bytes < %d x %zu needed", ws_bytes, lanes, lp.total);
+  int device = 0;
+  MG_HIP(hipGetDevice(&device));
+  if (!ctx->order_event && hipEventCreateWithFlags(&ctx->order_event, hipEventDisableTiming) != hipSuccess) {
+    ctx->order_event = nullptr;
+    return fail(MG_EHIP, "hipEventCreateWithFlags of the order event failed");
+  }
+  std::vector<mg_ctx*> made;
+  for (int w = 0; w < lanes; ++w) {
+    mg_ctx* lane = nullptr;
+    const int rc = make_lane(ctx, static_cast<unsigned char*>(workspace) + static_cast<size_t>(w) * lp.total, lp,
+                             device, &lane);
+    made.push_back(lane);
+    if (rc != MG_OK) {
+      for (mg_ctx* m : made) mg_destroy(m);
+      return rc;
+    }
+  }
+  ctx->lanes = made;
+  return MG_OK;
 }
 
 int mg_level_info(mg_ctx* ctx, int level, int* n, double* h) {

@@ -86,4 +86,47 @@ int build_plan(int n, int flags, Plan* plan) {
   return 0;
 }
 
+int build_lane_plan(int n, int flags, Plan* plan) {
+  Plan full;
+  if (build_plan(n, flags, &full) != 0 || !plan) return -1;
+  const bool mixed = (flags & kFlagMixed) != 0;
+  Plan p;
+  p.n = n;
+  p.flags = flags;
+  p.levels = full.levels;
+  Carver c;
+  for (int l = 0; l < p.levels; ++l) {
+    LevelPlan& lv = p.lv[l];
+    lv.n = full.lv[l].n;
+    lv.log2n = full.lv[l].log2n;
+    const size_t cells = static_cast<size_t>(lv.n) * lv.n * lv.n;
+    lv.bx = lv.by = lv.bz = lv.mask = kAbsent;
+    lv.bx32 = lv.by32 = lv.bz32 = kAbsent;
+    lv.f = l > 0 ? c.take(cells * 8) : kAbsent;
+    lv.e = l > 0 ? c.take(cells * 8) : kAbsent;
+    lv.t = c.take(cells * 8);
+    if (mixed) {
+      lv.f32 = c.take(cells * 4);
+      lv.e32 = c.take(cells * 4);
+      lv.t32 = c.take(cells * 4);
+    } else {
+      lv.f32 = lv.e32 = lv.t32 = kAbsent;
+    }
+  }
+  if (flags & kFlagKrylov) {
+    const size_t fine = static_cast<size_t>(n) * n * n * 8;
+    p.kr = c.take(fine);
+    p.kz = c.take(fine);
+    p.kd = c.take(fine);
+    p.kw = c.take(fine);
+  }
+  p.pinv = kAbsent;
+  p.partials = c.take(static_cast<size_t>(kPartialSets) * kNumPartials * 8);
+  p.scalars = c.take(32 * 8);
+  p.counters = kAbsent;
+  p.total = c.off;
+  *plan = p;
+  return 0;
+}
+
 }  // namespace mg

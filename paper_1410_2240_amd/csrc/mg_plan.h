@@ -59,4 +59,11 @@ int validate_dims(const int dims[3], int* n_out);
 // returns 0, or -1 for unsupported N or flags.
 int build_plan(int n, int flags, Plan* plan);
 
+// The arrays one solve writes (every grid's right-hand side, correction and second
+// buffers, the flexible-CG vectors, reduction partials and device scalars), laid out
+// on their own: the scratch of one more right-hand side solved concurrently with the
+// context's own.  Coefficients, masks and the pseudo-inverse are absent (kAbsent):
+// they are read-only during a solve and shared.  Returns 0, or -1 as build_plan.
+int build_lane_plan(int n, int flags, Plan* plan);
+
 }  // namespace mg

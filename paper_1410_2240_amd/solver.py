@@ -73,10 +73,12 @@ class MG:
 
     mixed: FP32 V-cycles inside FP64 refinement.  krylov: flexible CG preconditioned
     by one V-cycle per step (outer iteration), instead of plain V-cycle iteration.
+    lanes: extra streams on which a batched solve runs right-hand sides concurrently
+    (mg_add_lanes; each lane's scratch is one more workspace tensor slice).
     """
 
     def __init__(self, bx, by, bz, mask, h: float | None = None, mixed: bool = False, krylov: bool = False,
-                 _rho=None, _density_coarsening: bool = False):
+                 _rho=None, _density_coarsening: bool = False, lanes: int = 0):
         lib = _lib.load()
         ref = bx if _rho is None else _rho
         n = _grid_n(ref)
@@ -102,15 +104,22 @@ class MG:
         self._ctx = ctx
         self._destroy = lib.mg_destroy   # kept so that teardown at interpreter exit still finds it
         self.levels = lib.mg_level_info(ctx, 0, None, None)
+        self.lanes = int(lanes)
+        self.lane_workspace = None
+        if self.lanes > 0:
+            per = lib.mg_lane_workspace_size(_lib.dims3(n), flags)
+            self.lane_workspace = torch.empty(self.lanes * per, dtype=torch.uint8, device=ref.device)
+            _check(lib.mg_add_lanes(ctx, _ptr(self.lane_workspace), self.lanes * per, self.lanes), "mg_add_lanes")
 
     @classmethod
-    def from_rho(cls, rho, mask, h=None, mixed=False, krylov=False, coarsening="face"):
+    def from_rho(cls, rho, mask, h=None, mixed=False, krylov=False, coarsening="face", lanes=0):
         """Hierarchy from the cell density.  coarsening = "face" moves the face products
         to the coarse grids (section 3.1); "density" restricts density and areas apart,
         the variant the paper rejects (for comparison)."""
         if coarsening not in ("face", "density"):
             raise ValueError("coarsening must be 'face' or 'density'")
-        return cls(None, None, None, mask, h, mixed, krylov, _rho=rho, _density_coarsening=coarsening == "density")
+        return cls(None, None, None, mask, h, mixed, krylov, _rho=rho, _density_coarsening=coarsening == "density",
+                   lanes=lanes)
 
     def __del__(self):
         ctx = getattr(self, "_ctx", None)

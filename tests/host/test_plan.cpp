@@ -78,6 +78,53 @@ static void check_layout(int n, int flags) {
   }
 }
 
+// The scratch of one concurrent right-hand side: exactly the arrays a solve writes, with
+// the sizes the full plan gives them, disjoint and aligned; shared arrays absent.
+static void check_lane_layout(int n, int flags) {
+  mg::Plan full, p;
+  CHECK(mg::build_plan(n, flags, &full) == 0);
+  CHECK(mg::build_lane_plan(n, flags, &p) == 0);
+  CHECK(p.levels == full.levels);
+  CHECK(p.total % mg::kAlign == 0 && p.total < full.total);
+  std::vector<Span> spans;
+  for (int l = 0; l < p.levels; ++l) {
+    const mg::LevelPlan& a = p.lv[l];
+    CHECK(a.n == full.lv[l].n && a.log2n == full.lv[l].log2n);
+    const size_t c = static_cast<size_t>(a.n) * a.n * a.n;
+    for (size_t o : {a.bx, a.by, a.bz, a.mask, a.rt, a.rt32, a.bx32, a.by32, a.bz32}) CHECK(o == mg::kAbsent);
+    spans.push_back({a.t, c * 8});
+    if (l > 0) {
+      spans.push_back({a.f, c * 8});
+      spans.push_back({a.e, c * 8});
+    } else {
+      CHECK(a.f == mg::kAbsent && a.e == mg::kAbsent);
+    }
+    if (flags & 1) {
+      for (size_t o : {a.f32, a.e32, a.t32}) spans.push_back({o, c * 4});
+    } else {
+      CHECK(a.f32 == mg::kAbsent && a.e32 == mg::kAbsent && a.t32 == mg::kAbsent);
+    }
+  }
+  const size_t fine = static_cast<size_t>(n) * n * n * 8;
+  if (flags & 2) {
+    for (size_t o : {p.kr, p.kz, p.kd, p.kw}) spans.push_back({o, fine});
+  } else {
+    CHECK(p.kr == mg::kAbsent && p.kw == mg::kAbsent);
+  }
+  CHECK(p.pinv == mg::kAbsent && p.counters == mg::kAbsent);
+  spans.push_back({p.partials, static_cast<size_t>(mg::kPartialSets) * mg::kNumPartials * 8});
+  spans.push_back({p.scalars, 32 * 8});
+  for (size_t i = 0; i < spans.size(); ++i) {
+    CHECK(spans[i].off != mg::kAbsent);
+    CHECK(spans[i].off % mg::kAlign == 0);
+    CHECK(spans[i].off + spans[i].len <= p.total);
+    for (size_t j = i + 1; j < spans.size(); ++j) {
+      const bool disjoint = spans[i].off + spans[i].len <= spans[j].off || spans[j].off + spans[j].len <= spans[i].off;
+      CHECK(disjoint);
+    }
+  }
+}
+
 int main() {
   const int good[3] = {64, 64, 64};
   int n = 0;
@@ -89,7 +136,12 @@ int main() {
   CHECK(mg::build_plan(64, 8, &p) != 0);
   CHECK(mg::build_plan(64, -1, &p) != 0);
   for (int m : {8, 16, 64, 256})
-    for (int fl : {0, 1, 2, 3}) check_layout(m, fl);
+    for (int fl : {0, 1, 2, 3}) {
+      check_layout(m, fl);
+      check_lane_layout(m, fl);
+    }
+  CHECK(mg::build_lane_plan(48, 0, &p) != 0);
+  CHECK(mg::build_lane_plan(64, 8, &p) != 0);
   // density coarsening needs no storage of its own
   {
     mg::Plan pa, pb;

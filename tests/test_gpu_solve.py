@@ -199,6 +199,72 @@ def test_mixed_batch_and_warm_start_64():
     assert any(s % 2 for s in steps) and any(s % 2 == 0 for s in steps), steps
 
 
+@pytest.mark.parametrize("N,mixed,krylov,lanes", [(64, False, False, 2), (64, True, False, 2), (64, False, True, 3),
+                                                  (32, False, False, 1), (128, False, False, 3)])
+def test_lanes_give_the_one_by_one_results(N, mixed, krylov, lanes):
+    """A batch solved on 1 + lanes concurrent streams: every item's solution and history
+    bit for bit those of the one-at-a-time loop (five items, so lanes get unequal
+    shares), the solutions within the bar of the exact ones, and the caller's stream
+    ordered after the lanes (the comparison below runs on it without a sync)."""
+    from paper_1410_2240_amd import MG
+    inp, H = workload("c1", N)
+    fb = fields.batch_rhs(inp.mask, 5)
+    one = MG.from_rho(dev(inp.rho), dev(inp.mask), mixed=mixed, krylov=krylov)
+    par = MG.from_rho(dev(inp.rho), dev(inp.mask), mixed=mixed, krylov=krylov, lanes=lanes)
+    p1, h1, s1 = one.solve(dev(fb), tol=1e-12)
+    pl, hl, sl = par.solve(dev(fb), tol=1e-12)
+    assert torch.equal(p1, pl)
+    assert h1 == hl and s1["cycles"] == sl["cycles"] and s1["status"] == sl["status"] == 0
+    for b in (0, 4):
+        assert relerr(host(pl[b]), exact.solve_fft_z(H.fine, fb[b])) <= 1e-9
+    # a second batch on the same lanes, and a single item (no lane used)
+    p2, h2, _ = par.solve(dev(fb[:2]), tol=1e-12)
+    assert torch.equal(p2, p1[:2]) and h2 == h1[:2]
+    p3, h3, _ = par.solve(dev(fb[3]), tol=1e-12)
+    assert torch.equal(p3, p1[3]) and h3 == h1[3]
+
+
+def test_lanes_report_statuses_in_batch_order():
+    """Items that stop early on lanes: the same statuses, histories and first message as
+    the one-at-a-time loop; argument errors before any work; lanes added once only."""
+    from paper_1410_2240_amd import MG, MGError
+    from paper_1410_2240_amd import _lib
+    inp, _ = workload("c1", 64)
+    fb = fields.batch_rhs(inp.mask, 4)
+    bad = fb.copy()
+    bad[2, 3, 3, 3] = np.nan
+    one = MG.from_rho(dev(inp.rho), dev(inp.mask))
+    par = MG.from_rho(dev(inp.rho), dev(inp.mask), lanes=3)
+    for f, code in ((fb, _lib.MG_ENOCONV), (bad, _lib.MG_EBREAKDOWN)):
+        maxc = 2 if code == _lib.MG_ENOCONV else 100
+        r1 = one.solve(dev(f), tol=1e-12, max_cycles=maxc, raise_on_fail=False)
+        m1 = _lib.last_error()
+        rl = par.solve(dev(f), tol=1e-12, max_cycles=maxc, raise_on_fail=False)
+        ml = _lib.last_error()
+        assert r1[2]["status"] == rl[2]["status"] == code
+        assert r1[1] == rl[1] and torch.equal(r1[0], rl[0])
+        assert ml and m1 == ml
+    with pytest.raises(MGError) as ei:
+        par.solve(dev(fb), tol=-1.0)
+    assert ei.value.code == _lib.MG_EINVAL
+    lib = _lib.load()
+    assert lib.mg_add_lanes(par._ctx, _ptr_of(par.lane_workspace), par.lane_workspace.numel(), 1) == _lib.MG_EINVAL
+    assert "already" in _lib.last_error()
+    per = lib.mg_lane_workspace_size(_lib.dims3(64), 0)
+    small = torch.empty(per, dtype=torch.uint8, device="cuda")
+    assert lib.mg_add_lanes(one._ctx, _ptr_of(small), per, 2) == _lib.MG_EWORKSPACE
+    assert lib.mg_add_lanes(one._ctx, _ptr_of(small), per, 0) == _lib.MG_EINVAL
+    assert lib.mg_add_lanes(one._ctx, _ptr_of(small), per, _lib.MG_MAX_LANES + 1) == _lib.MG_EINVAL
+    # the failed calls left the context without lanes: a batch still solves one by one
+    p, h, st = one.solve(dev(fb[:2]), tol=1e-12)
+    assert st["status"] == 0
+
+
+def _ptr_of(t):
+    import ctypes
+    return ctypes.c_void_p(t.data_ptr())
+
+
 # ------------------------------------------------------------------ error paths
 
 def test_errors_reported():
