@@ -178,6 +178,7 @@ def main():
         torch.cuda.empty_cache()
     log(f"coarsening ablation {abl}")
     cut = cut_cell_leg(N, args) if args.config == "c2" else None
+    diff = differentiation_leg(args) if args.config == "c2" else None
     traffic = recorded_traffic(inp.name, N)
     out = {
         "metric": "grid-pts/s per V-cycle (FP64 projection: setup + solve to 1e-10)",
@@ -196,6 +197,7 @@ def main():
         "krylov_fcg": kr,
         "coarsening_ablation": abl,
         "cut_cells": cut,
+        "differentiation": diff,
         "vcycle_ms": {"fp64": vc64, "fp32": vc32},
         "vcycle_pts_per_s": {"fp64": n / (vc64 * 1e-3), "fp32": n / (vc32 * 1e-3)},
         # algorithmic scalars per finest cell per V(2,2) cycle: the FP64 finest grid reads
@@ -248,6 +250,46 @@ def cut_cell_leg(N, args):
            "fcg_steps": st["cycles"], "fcg_status": st["status"], "final_relres": hist[-1],
            "setup_plus_solve_ms": (time.time() - t0) * 1e3, "rhs": "P(N(0,1)) merged"}
     log(f"cut cells {out}")
+    return out
+
+
+def differentiation_leg(args):
+    """The differentiated projection: 8 right-hand sides at 128^3 (flat interface),
+    poisson_solve forward (setup + 8 solves) and the backward of L = sum w.p (8 adjoint
+    solves + the coefficient gradient), one right-hand side at a time and with the
+    default concurrent lanes; best of two, and whether the two give the same bits."""
+    import torch
+    import fields
+    from paper_1410_2240_amd.autograd import DEFAULT_CONCURRENCY, poisson_solve
+    N, B = 128, 8
+    inp = fields.make("c4", N)
+    rho = torch.from_numpy(inp.rho).cuda().requires_grad_(True)
+    mask = torch.from_numpy(inp.mask).cuda()
+    fb = torch.from_numpy(fields.batch_rhs(inp.mask, B)).cuda().requires_grad_(True)
+    w = torch.from_numpy(fields.adjoint_weights(N, B)).cuda()
+    out = {"workload": "c4_flat_128_batch8", "tol": args.tol, "concurrency": DEFAULT_CONCURRENCY}
+    for prec in ("fp64", "mixed"):
+        res = {}
+        for lanes in (0, None):
+            best_f = best_b = float("inf")
+            for _ in range(2):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                p = poisson_solve(fb, rho, mask, tol=args.tol, precision=prec, lanes=lanes)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                gf, grho = torch.autograd.grad((w * p).sum(), (fb, rho))
+                torch.cuda.synchronize()
+                t2 = time.perf_counter()
+                best_f, best_b = min(best_f, t1 - t0), min(best_b, t2 - t1)
+            res["one_at_a_time" if lanes == 0 else "concurrent"] = {
+                "forward_ms": best_f * 1e3, "backward_ms": best_b * 1e3, "out": (p.detach(), gf, grho)}
+        a, b = res["one_at_a_time"].pop("out"), res["concurrent"].pop("out")
+        res["identical"] = all(torch.equal(x, y) for x, y in zip(a, b))
+        out[prec] = res
+        del a, b
+    torch.cuda.empty_cache()
+    log(f"differentiation {out}")
     return out
 
 
