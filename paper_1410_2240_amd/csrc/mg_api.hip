@@ -745,10 +745,16 @@ int solve_lanes(mg_ctx* ctx, const double* f, double* p, int batch, double tol, 
   MG_HIP(hipEventRecord(ctx->order_event, ctx->stream));
   for (int w = 1; w < W; ++w) MG_HIP(hipStreamWaitEvent(ctx->lanes[w - 1]->stream, ctx->order_event, 0));
   std::vector<std::thread> threads;
-  threads.reserve(W - 1);
-  for (int w = 1; w < W; ++w)
-    threads.emplace_back(run_lane, ctx->lanes[w - 1], w, W, f, p, batch, n3, tol, max_cycles, hist, &res);
+  std::vector<int> unthreaded;   // lanes whose thread could not be started
+  for (int w = 1; w < W; ++w) {
+    try {
+      threads.emplace_back(run_lane, ctx->lanes[w - 1], w, W, f, p, batch, n3, tol, max_cycles, hist, &res);
+    } catch (...) {   // nothing may be thrown across the C ABI: run that lane from here
+      unthreaded.push_back(w);
+    }
+  }
   run_lane(ctx, 0, W, f, p, batch, n3, tol, max_cycles, hist, &res);
+  for (int w : unthreaded) run_lane(ctx->lanes[w - 1], w, W, f, p, batch, n3, tol, max_cycles, hist, &res);
   for (auto& t : threads) t.join();
   int rc = MG_OK;
   for (int w = 1; w < W; ++w) {
