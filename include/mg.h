@@ -33,7 +33,9 @@
  *
  * Streams.  All device work is ordered on the HIP stream given to mg_setup (or set
  * later with mg_set_stream); NULL means the default stream.  Entry points that
- * report numbers to the host (mg_setup, mg_solve) synchronise that stream.
+ * report numbers to the host (mg_setup, mg_solve) synchronise that stream.  A context
+ * with lanes (mg_add_lanes) also runs batch items on its lanes' own streams, joined to
+ * that stream at the start and end of each mg_solve.
  *
  * Errors.  Every int-returning function returns MG_OK or a negative code and never
  * throws across the ABI; mg_last_error() returns a thread-local message.  Invalid
