@@ -26,6 +26,8 @@
 // wherever a face touches an inactive cell or a wall and otherwise bit for bit the
 // stored coefficient.  That is 4 scalars per cell per sweep instead of 6, for nine
 // reciprocals per x-pair and plane (each face once).
+#include <algorithm>
+
 #include "mg_buffer.h"
 #include "mg_kernels.h"
 
@@ -605,11 +607,14 @@ hipError_t launch_tx(const T* pin, T* pout, const T* f, const T* bx, const T* by
   const int n = 1 << q;
   constexpr int threads = TX / 2 * TY;
   const long long tiles = static_cast<long long>(n / TX) * (n / TY);
-  // z-chunk: as long as possible (overlap planes per chunk) while still giving each
-  // compute unit the workgroups it can hold at once (FP64 needs about twice the
-  // registers of FP32, so half as many fit)
-  const long long want = 256LL * 1024 / threads / (sizeof(T) == 8 ? 2 : 1);
-  int kc = 32;
+  // z-chunk: as long as possible while every compute unit still gets `want`
+  // workgroups at once: 256 compute units x one workgroup of 1024 threads, or of
+  // smaller ones as many as fit (FP64 fits half as many as FP32).  Each chunk pays a
+  // prologue of two extra planes and a full load latency before its march settles
+  // (about 17 us per chunk, from 32-plane against whole-column chunks at 512^3), so
+  // on 512^3 and 1024^3 grids a chunk spans the whole z column.
+  const long long want = 256LL * std::max(1, 1024 / threads / (sizeof(T) == 8 ? 2 : 1));
+  int kc = n;
   while (kc > 4 && tiles * (n / kc) < want) kc /= 2;
   if (kc > n) kc = n;
   const long long blocks = tiles * (n / kc);
