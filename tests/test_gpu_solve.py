@@ -224,6 +224,28 @@ def test_lanes_give_the_one_by_one_results(N, mixed, krylov, lanes):
     assert torch.equal(p3, p1[3]) and h3 == h1[3]
 
 
+def test_lanes_follow_the_callers_stream():
+    """On a side stream: the right-hand sides are produced there just before the call,
+    and the solutions are consumed there just after it, with no synchronisation in
+    between.  Lanes must start after the first and finish before the second."""
+    from paper_1410_2240_amd import MG
+    inp, _ = workload("c1", 64)
+    fb = dev(fields.batch_rhs(inp.mask, 4))
+    ref, _, _ = MG.from_rho(dev(inp.rho), dev(inp.mask)).solve(fb, tol=1e-12)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        par = MG.from_rho(dev(inp.rho), dev(inp.mask), lanes=3)
+        for _ in range(2):
+            f = torch.empty_like(fb)
+            f.copy_(fb * 2.0)            # queued on the side stream just before the solve
+            p, _, st = par.solve(f, tol=1e-12)
+            q = p * 0.5                  # queued on the side stream just after it
+    torch.cuda.synchronize()
+    assert st["status"] == 0
+    assert torch.equal(q, ref)   # scaling by 2 is exact in every step of the solve
+
+
 def test_lanes_report_statuses_in_batch_order():
     """Items that stop early on lanes: the same statuses, histories and first message as
     the one-at-a-time loop; argument errors before any work; lanes added once only."""
