@@ -180,8 +180,8 @@ int mg_solve(mg_ctx* ctx, const double* f, double* p, int batch, double tol, int
  * each extra lane driven by a host thread of its own.  The lane streams start after the
  * work already queued on ctx's stream, and ctx's stream waits for all of them before
  * anything queued after mg_solve.  Errors: MG_EINVAL (null ctx, lanes out of range, lanes
- * already added), MG_EWORKSPACE (workspace null, misaligned or too small), MG_EHIP.  On
- * error no lane is added.
+ * already added, or a current device other than that of ctx's stream), MG_EWORKSPACE
+ * (workspace null, misaligned or too small), MG_EHIP.  On error no lane is added.
  */
 #define MG_MAX_LANES 16
 size_t mg_lane_workspace_size(const int dims[3], int flags);

@@ -976,6 +976,13 @@ int mg_add_lanes(mg_ctx* ctx, void* workspace, size_t ws_bytes, int lanes) {
     return fail(MG_EWORKSPACE, "workspace %zu bytes < %d x %zu needed", ws_bytes, lanes, lp.total);
   int device = 0;
   MG_HIP(hipGetDevice(&device));
+  if (ctx->stream) {   // the lanes' streams must live on the device of the context's stream
+    hipDevice_t sdev = 0;
+    MG_HIP(hipStreamGetDevice(ctx->stream, &sdev));
+    if (static_cast<int>(sdev) != device)
+      return fail(MG_EINVAL, "the context's stream is on device %d, the current device is %d", static_cast<int>(sdev),
+                  device);
+  }
   if (!ctx->order_event && hipEventCreateWithFlags(&ctx->order_event, hipEventDisableTiming) != hipSuccess) {
     ctx->order_event = nullptr;
     return fail(MG_EHIP, "hipEventCreateWithFlags of the order event failed");
