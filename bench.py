@@ -44,6 +44,9 @@ def parse():
                     help="only run a plain 512 MiB device copy (HBM counter calibration) and exit")
     ap.add_argument("--oracle-timing", action="store_true",
                     help="only time the CPU oracle on this host (multigrid 32^3..256^3, FFT+Thomas 512^3) and exit")
+    ap.add_argument("--coarsening-sweep", action="store_true",
+                    help="only compare the two coarsenings of section 3.1 on the wavy field from 32^3 to 1024^3 "
+                         "(cycles and contraction factor of plain V-cycles, flexible-CG steps) and exit")
     return ap.parse_args()
 
 
@@ -59,6 +62,9 @@ def main():
         sys.exit(2)
     if args.oracle_timing:
         print(json.dumps(oracle_timing()))
+        return
+    if args.coarsening_sweep:
+        print(json.dumps(coarsening_sweep(args)))
         return
     import numpy as np
     import torch
@@ -290,6 +296,49 @@ def differentiation_leg(args):
         del a, b
     torch.cuda.empty_cache()
     log(f"differentiation {out}")
+    return out
+
+
+def coarsening_sweep(args):
+    """Section 3.1's claim across grid sizes: the face products coarsened as one unit
+    against the density restricted cell centre to cell centre (areas apart), on the
+    wavy interface + body field from 32^3 to 1024^3.  Per N and coarsening: plain
+    V-cycles (at most 100) with their status, cycles and asymptotic contraction factor
+    (geometric mean of the last five residual ratios), and flexible-CG steps to tol."""
+    import numpy as np
+    import torch
+    import fields
+    from paper_1410_2240_amd import MG
+    out = {"workload": "c2_wavy_body", "tol": args.tol, "max_vcycles": 100, "sizes": {}}
+    for N in (32, 64, 128, 256, 512, 1024):
+        t0 = time.time()
+        inp = fields.make("c2", N)
+        rho = torch.from_numpy(inp.rho).cuda()
+        mask = torch.from_numpy(inp.mask).cuda()
+        f = torch.from_numpy(inp.f).cuda()
+        del inp
+        log(f"coarsening sweep {N}^3: inputs in {time.time() - t0:.1f} s")
+        row = {}
+        for mode in ("face", "density"):
+            mg = MG.from_rho(rho, mask, coarsening=mode)
+            _, h, st = mg.solve(f, tol=args.tol, max_cycles=100, raise_on_fail=False)
+            del mg
+            tail = [b / a for a, b in zip(h[:-1], h[1:]) if a > 0][-5:]
+            rate = float(np.prod(tail) ** (1.0 / len(tail))) if tail else None
+            torch.cuda.synchronize()
+            t1 = time.time()
+            mgk = MG.from_rho(rho, mask, krylov=True, coarsening=mode)
+            _, hk, stk = mgk.solve(f, tol=args.tol, max_cycles=200, raise_on_fail=False)
+            torch.cuda.synchronize()
+            del mgk
+            torch.cuda.empty_cache()
+            row[mode] = {"vcycle_status": st["status"], "vcycles": st["cycles"], "vcycle_final_relres": h[-1],
+                         "vcycle_rate": rate, "fcg_status": stk["status"], "fcg_steps": stk["cycles"],
+                         "fcg_final_relres": hk[-1], "fcg_ms": (time.time() - t1) * 1e3}
+            log(f"  {mode}: {row[mode]}")
+        out["sizes"][str(N)] = row
+        del rho, mask, f
+        torch.cuda.empty_cache()
     return out
 
 
