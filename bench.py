@@ -185,6 +185,7 @@ def main():
     log(f"coarsening ablation {abl}")
     cut = cut_cell_leg(N, args) if args.config == "c2" else None
     diff = differentiation_leg(args) if args.config == "c2" else None
+    rk2 = rk2_leg(N, args) if args.config == "c2" else None
     traffic = recorded_traffic(inp.name, N)
     out = {
         "metric": "grid-pts/s per V-cycle (FP64 projection: setup + solve to 1e-10)",
@@ -204,6 +205,7 @@ def main():
         "coarsening_ablation": abl,
         "cut_cells": cut,
         "differentiation": diff,
+        "rk2_projection": rk2,
         "vcycle_ms": {"fp64": vc64, "fp32": vc32},
         "vcycle_pts_per_s": {"fp64": n / (vc64 * 1e-3), "fp32": n / (vc32 * 1e-3)},
         # algorithmic scalars per finest cell per V(2,2) cycle: the FP64 finest grid reads
@@ -296,6 +298,70 @@ def differentiation_leg(args):
         del a, b
     torch.cuda.empty_cache()
     log(f"differentiation {out}")
+    return out
+
+
+def rk2_leg(N, args):
+    """The pressure projection of one two-stage Runge-Kutta step (section 2.1: a
+    projection after each stage, eqs. runge1 / runge2) on the bench field.  Each stage
+    sets the hierarchy up from rho (the density changes every stage in the flow solver),
+    forms f = div(U + dt R)/dt from the face velocities, solves, and projects; the
+    second stage starts from the first stage's pressure.  Inputs (seeded): U^n = seeded
+    N(0, 1) face velocities made divergence-free by one untimed projection, as after the
+    previous step; R1 = N(0, 1) per face; R2 = R1 + 0.01 N(0, 1), the forcing evaluated
+    again at the intermediate velocity; dt = 1e-3.  Reports the step time, each stage's
+    cycles, the second stage's cycles from p = 0 for comparison, and the largest
+    divergence left, relative to the largest source."""
+    import torch
+    from paper_1410_2240_amd import MG
+    import fields
+    inp = fields.make("c2", N)
+    rho = torch.from_numpy(inp.rho).cuda()
+    mask = torch.from_numpy(inp.mask).cuda()
+    del inp
+    g = torch.Generator(device="cuda").manual_seed(1410)
+    shape = (N, N, N)
+    def randn():
+        return torch.randn(shape, dtype=torch.float64, device="cuda", generator=g)
+    U = tuple(randn() for _ in range(3))
+    R1 = tuple(randn() for _ in range(3))
+    R2 = tuple(r + 0.01 * randn() for r in R1)
+    dt = 1e-3
+    prep = MG.from_rho(rho, mask)
+    p0, _, _ = prep.solve(prep.divergence(U, None, 1.0), tol=1e-12, max_cycles=100)
+    prep.project(U, p0, None, 1.0)
+    del prep, p0
+    out = {"workload": f"c2_wavy_body_{N}", "dt": dt, "tol": args.tol}
+    for prec in ("fp64", "mixed"):
+        mixed = prec == "mixed"
+        best, res = float("inf"), None
+        for _ in range(3):
+            V = tuple(u.clone() for u in U)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            mg1 = MG.from_rho(rho, mask, mixed=mixed)
+            f1 = mg1.divergence(V, R1, dt)
+            p1, h1, _ = mg1.solve(f1, tol=args.tol, max_cycles=args.max_cycles, raise_on_fail=False)
+            mg1.project(V, p1, R1, dt)
+            mg2 = MG.from_rho(rho, mask, mixed=mixed)
+            f2 = mg2.divergence(V, R2, dt)
+            p2, h2, _ = mg2.solve(f2, p=p1.clone(), tol=args.tol, max_cycles=args.max_cycles, raise_on_fail=False)
+            mg2.project(V, p2, R2, dt)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            if t < best:
+                best = t
+                div = mg2.divergence(V, None, 1.0)
+                res = {"step_ms": t * 1e3, "stage1_cycles": len(h1) - 1, "stage2_cycles_warm": len(h2) - 1,
+                       "max_div_rel": float(div.abs().max()) / (float(f2.abs().max()) * dt)}
+            del mg1, mg2
+        mgc = MG.from_rho(rho, mask, mixed=mixed)
+        _, hc, _ = mgc.solve(f2, tol=args.tol, max_cycles=args.max_cycles, raise_on_fail=False)
+        res["stage2_cycles_cold"] = len(hc) - 1
+        del mgc
+        out[prec] = res
+    torch.cuda.empty_cache()
+    log(f"rk2 projection {out}")
     return out
 
 
