@@ -25,6 +25,12 @@ other choice is a reading, written here plainly:
 Mixed precision (not in the paper): one FP32 V-cycle per step of FP64 iterative
 refinement; the residual, the update and the coarsest solve stay FP64, and the FP32
 face coefficients are the FP64 ones rounded to nearest.
+
+Pins: every step (smoother, transfers, coarsening, coarsest solve) against closed
+forms, identities and library routines, and the converged solution against the exact
+solvers of oracle.exact.  Parity unpinned: the convergence rate, i.e. the residual
+history cycle by cycle.  The paper prints no history, so only the GPU's agreement
+with this module pins it.
 """
 from __future__ import annotations
 
