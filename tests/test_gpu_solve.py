@@ -266,6 +266,13 @@ def test_lanes_report_statuses_in_batch_order():
         assert r1[2]["status"] == rl[2]["status"] == code
         assert r1[1] == rl[1] and torch.equal(r1[0], rl[0])
         assert ml and m1 == ml
+    # a zero right-hand side among others: p = 0 and the history [0] for it alone
+    zf = fb.copy()
+    zf[1] = 0.0
+    pz, hz, sz = par.solve(dev(zf), tol=1e-12)
+    p1, h1, _ = one.solve(dev(zf), tol=1e-12)
+    assert sz["status"] == 0 and hz[1] == [0.0] and not host(pz[1]).any()
+    assert torch.equal(pz, p1) and hz == h1
     with pytest.raises(MGError) as ei:
         par.solve(dev(fb), tol=-1.0)
     assert ei.value.code == _lib.MG_EINVAL
