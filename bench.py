@@ -44,6 +44,8 @@ def parse():
                     help="only run a plain 512 MiB device copy (HBM counter calibration) and exit")
     ap.add_argument("--oracle-timing", action="store_true",
                     help="only time the CPU oracle on this host (multigrid 32^3..256^3, FFT+Thomas 512^3) and exit")
+    ap.add_argument("--level-breakdown", action="store_true",
+                    help="only time each grid's share of a V(2,2) cycle on the bench field and exit")
     ap.add_argument("--coarsening-sweep", action="store_true",
                     help="only compare the two coarsenings of section 3.1 on the wavy field from 32^3 to 1024^3 "
                          "(cycles and contraction factor of plain V-cycles, flexible-CG steps) and exit")
@@ -65,6 +67,9 @@ def main():
         return
     if args.coarsening_sweep:
         print(json.dumps(coarsening_sweep(args)))
+        return
+    if args.level_breakdown:
+        print(json.dumps(level_breakdown(args)))
         return
     import numpy as np
     import torch
@@ -362,6 +367,66 @@ def rk2_leg(N, args):
         out[prec] = res
     torch.cuda.empty_cache()
     log(f"rk2 projection {out}")
+    return out
+
+
+def level_breakdown(args):
+    """Where a V(2,2) cycle spends its time on the bench field: per grid with a coarser
+    one below it (down to 32^3), the four sweeps, the residual + restriction and the
+    prolongation, each timed through the component entry points with HIP events (best
+    of the mean of 20 calls); the single-workgroup tail (16^3 and below) is the whole
+    cycle minus those.  FP64 cycle, and the FP32 cycle of a mixed context."""
+    import torch
+    import fields
+    from paper_1410_2240_amd import MG
+    N = args.n or 256
+    inp = fields.make(args.config, N)
+    rho = torch.from_numpy(inp.rho).cuda()
+    mask = torch.from_numpy(inp.mask).cuda()
+    f0 = torch.from_numpy(inp.f).cuda()
+    del inp
+
+    def tm(fn, reps=20):
+        fn()
+        torch.cuda.synchronize()
+        best = float("inf")
+        for _ in range(3):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(reps):
+                fn()
+            b.record()
+            torch.cuda.synchronize()
+            best = min(best, a.elapsed_time(b) / reps)
+        return best * 1e3   # us
+
+    out = {"workload": f"{args.config}_{N}"}
+    g = torch.Generator(device="cuda").manual_seed(1410)
+    for prec, mixed, dt in (("fp64", False, torch.float64), ("fp32", True, torch.float32)):
+        mg = MG.from_rho(rho, mask, mixed=mixed)
+        grids, above = [], 0.0
+        for lv in range(mg.levels - 1):
+            n_l, _ = mg.level_info(lv)
+            if n_l <= 16:
+                break
+            p = torch.zeros((n_l,) * 3, dtype=dt, device="cuda")
+            f = f0.to(dt) if lv == 0 else torch.randn((n_l,) * 3, dtype=torch.float64, device="cuda",
+                                                       generator=g).to(dt)
+            ec = torch.zeros((n_l // 2,) * 3, dtype=dt, device="cuda")
+            sweeps = 2 * tm(lambda: mg.smooth(lv, p, f, 2, 0))
+            rr = tm(lambda: mg.residual_restrict(lv, p, f))
+            pro = tm(lambda: mg.prolong_add(lv, ec, p))
+            grids.append({"n": n_l, "sweeps_us": sweeps, "residual_restrict_us": rr, "prolong_us": pro,
+                          "total_us": sweeps + rr + pro})
+            above += sweeps + rr + pro
+            del p, f, ec
+        pf = torch.zeros_like(f0, dtype=dt)
+        ff = f0.to(dt)
+        cycle = tm(lambda: mg.vcycle(pf, ff))
+        out[prec] = {"cycle_us": cycle, "grids": grids, "tail_us": cycle - above}
+        log(f"level breakdown {prec}: {out[prec]}")
+        del mg, pf, ff
+        torch.cuda.empty_cache()
     return out
 
 
