@@ -96,21 +96,25 @@ def test_flat_128_mixed_matches_fft():
 
 def test_flat_512_fp64_and_mixed_match_fft_exact():
     """The 512^3 mixed-precision workload at its full size (1-cell smear, density ratio
-    1000): FP64 V-cycles and FP32 cycles inside FP64 refinement, both to 1e-12, against
-    the oracle's exact FFT + Thomas solution."""
+    1000): FP64 V-cycles and FP32 cycles inside FP64 refinement, and flexible CG with
+    either cycle, all to 1e-12, against the oracle's exact FFT + Thomas solution (the
+    sweeps march whole z columns at this size)."""
     import fields as F
     from oracle.operator import Level, face_coeffs_from_rho
+    from paper_1410_2240_amd import MG
     inp = F.make("c3", 512)
     print("512^3 c3: oracle FFT solve", flush=True)
     lev = Level(*face_coeffs_from_rho(inp.rho, inp.mask), inp.mask.astype(bool), inp.h)
     pe = exact.solve_fft_z(lev, inp.f)
     del lev
     for mixed in (False, True):
-        print(f"512^3 c3: GPU solve mixed={mixed}", flush=True)
-        p, hist, st = mg_from_inputs(inp, mixed).solve(dev(inp.f), tol=1e-12, max_cycles=100)
-        assert relerr(host(p), pe) <= 1e-9, (mixed, hist[-1])
-        del p
-        torch.cuda.empty_cache()
+        for krylov in (False, True):
+            print(f"512^3 c3: GPU solve mixed={mixed} krylov={krylov}", flush=True)
+            mg = MG.from_rho(dev(inp.rho), dev(inp.mask), mixed=mixed, krylov=krylov)
+            p, hist, st = mg.solve(dev(inp.f), tol=1e-12, max_cycles=100)
+            assert relerr(host(p), pe) <= 1e-9, (mixed, krylov, hist[-1])
+            del p, mg
+            torch.cuda.empty_cache()
 
 
 def test_bench_workload_256_residual_by_oracle():
