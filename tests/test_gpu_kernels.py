@@ -223,3 +223,27 @@ def test_fused_sweep_fp32(problem128, order):
     want = omg.smooth(p, f, lev32, 2, (omg.RED, omg.BLACK) if order == 0 else (omg.BLACK, omg.RED))
     got = host(mg.smooth(0, dev(p), dev(f), 2, order))
     assert maxrel(got, want) <= TOL32
+
+
+@pytest.mark.slow
+def test_fused_sweep_512_whole_columns_matches_oracle():
+    """From 512^3 up each workgroup sweeps its tile's whole z column in one chunk, with
+    no chunk boundary: one FP64 density-form sweep of the bench field (wavy interface +
+    body) at 512^3 against the oracle's two half-sweeps, every element."""
+    import fields
+    from oracle.operator import Level, diagonal
+    from paper_1410_2240_amd import MG
+    N = 512
+    inp = fields.make("c2", N)
+    print("512^3 sweep: oracle", flush=True)
+    lev = Level(*orho(inp.rho, inp.mask), inp.mask.astype(bool), inp.h)
+    lev.mask = lev.mask & (diagonal(lev) > 0)
+    g = np.random.default_rng(512)
+    p = np.where(lev.mask, g.standard_normal((N, N, N)), 0.0)
+    f = g.standard_normal((N, N, N))
+    want = omg.smooth(p, f, lev, 1, (omg.RED, omg.BLACK))
+    del lev
+    print("512^3 sweep: GPU", flush=True)
+    mg = MG.from_rho(dev(inp.rho), dev(inp.mask))
+    got = host(mg.smooth(0, dev(p), dev(f), 1, 0))
+    assert maxrel(got, want) <= TOL64
