@@ -98,8 +98,8 @@ def test_mixed_density_form_converges_to_the_same_solution(krylov):
     assert relerr(host(pa), host(pb)) <= 1e-9
 
 
-@pytest.mark.parametrize("N", [64, 128, 256])
-@pytest.mark.parametrize("order", [0, 1])
+@pytest.mark.parametrize("N,order", [(64, 0), (64, 1), (128, 0), (128, 1), (256, 0), (256, 1),
+                                     pytest.param(512, 0, marks=pytest.mark.slow)])
 def test_fp32_density_sweep_matches_emulation(N, order):
     """The FP32 density-form sweep against the oracle's float32 Gauss-Seidel on the
     operator formed from the density in single precision."""
