@@ -193,7 +193,10 @@ def main():
     rk2 = rk2_leg(N, args) if args.config == "c2" else None
     traffic = recorded_traffic(inp.name, N)
     out = {
-        "metric": "grid-pts/s per V-cycle (FP64 projection: setup + solve to 1e-10)",
+        "metric": "grid-pts/s per V-cycle + time-to-1e-10 residual (FP64 vs mixed), % HBM peak",
+        "value_definition": "grid points x V-cycles / time of the FP64 projection (setup from rho + solve to "
+                            "1e-10 from p = 0); time_to_tol_ms gives FP64 and mixed, roofline and "
+                            "vcycle_roofline_frac the fraction of HBM peak",
         "value": n * cyc64 / (ms64 * 1e-3),
         "unit": "grid-pts/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
