@@ -23,8 +23,10 @@ other choice is a reading, written here plainly:
   * stopping: relative residual ||P f - A p||_2 / ||P f||_2 after every cycle;
   * gauge: the returned p has zero mean over active cells and is 0 in the body.
 Mixed precision (not in the paper): one FP32 V-cycle per step of FP64 iterative
-refinement; the residual, the update and the coarsest solve stay FP64, and the FP32
-face coefficients are the FP64 ones rounded to nearest.
+refinement; the residual, the update and the coarsest solve stay FP64.  The FP32 face
+coefficients of the coarse grids are the FP64 ones rounded to nearest; the finest FP32
+grid either rounds its FP64 coefficients too (fp32_levels) or forms them in single
+precision from fl32(rho) (fp32_levels_from_rho), within two float32 ulps of rounding.
 
 Pins: every step (smoother, transfers, coarsening, coarsest solve) against closed
 forms, identities and library routines, and the converged solution against the exact
@@ -259,10 +261,21 @@ def fp32_density_level(rho, lev: Level) -> Level:
     return Level(bx, by, bz, lev.mask.copy(), lev.h)
 
 
-def solve_mixed(hier: Hierarchy, f, p0=None, tol: float = 1e-10, max_steps: int = 100):
-    """FP64 iterative refinement with one FP32 V-cycle per step (coarsest solve FP64)."""
+def fp32_levels_from_rho(hier: Hierarchy, rho) -> list:
+    """The FP32 hierarchy of cycles that work from the density on the finest grid:
+    the finest grid from fl32(rho) (fp32_density_level), every coarser grid the FP64
+    coarse coefficients rounded to nearest (they exist only as face products)."""
+    return [fp32_density_level(rho, hier.fine)] + [lev.astype(np.float32) for lev in hier.levels[1:]]
+
+
+def solve_mixed(hier: Hierarchy, f, p0=None, tol: float = 1e-10, max_steps: int = 100, lv32=None):
+    """FP64 iterative refinement with one FP32 V-cycle per step (coarsest solve FP64).
+
+    lv32: the FP32 hierarchy of the cycles; by default the FP64 coefficients of every
+    grid rounded to nearest (fp32_levels), or fp32_levels_from_rho for cycles whose
+    finest operator is formed from the density in single precision."""
     lev = hier.fine
-    lv32 = fp32_levels(hier)
+    lv32 = fp32_levels(hier) if lv32 is None else lv32
     fhat = project(np.asarray(f, np.float64), lev.mask)
     nf = float(np.sqrt(np.sum(fhat * fhat)))
     p = np.zeros_like(fhat) if p0 is None else np.where(lev.mask, p0, 0.0)
@@ -287,7 +300,7 @@ def contraction(hist, skip: int = 2) -> float:
 
 
 def solve_fcg(hier: Hierarchy, f, p0=None, tol: float = 1e-10, max_iters: int = 100, mixed: bool = False,
-              precond=None):
+              precond=None, lv32=None):
     """Flexible conjugate gradients on the negative semi-definite A, preconditioned by
     one V(2,2) cycle from a zero guess (FP32 cycle when mixed), everything else FP64.
 
@@ -308,7 +321,8 @@ def solve_fcg(hier: Hierarchy, f, p0=None, tol: float = 1e-10, max_iters: int = 
         return np.zeros_like(fhat), [0.0]
     nf = float(np.sqrt(np.sum(fhat * fhat)))
     p = np.zeros_like(fhat) if p0 is None else np.where(lev.mask, p0, 0.0)
-    lv32 = fp32_levels(hier) if mixed else None
+    if mixed and lv32 is None:
+        lv32 = fp32_levels(hier)
 
     def V(r):
         if precond is not None:

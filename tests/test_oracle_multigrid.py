@@ -367,3 +367,22 @@ def test_rhs_without_range_component_gives_zero():
     assert not omg.zero_range(f, project(f, H.fine.mask), H.fine.mask)
     _, hist = omg.solve(H, f, tol=1e-8)
     assert hist[0] == 1.0 and hist[-1] <= 1e-8
+
+
+def test_mixed_refinement_on_density_form_fp32_operator():
+    """Mixed refinement whose FP32 finest operator is formed from fl32(rho), as the
+    cycles of a hierarchy set up from the density do on grids swept in one pass: it
+    reaches the exact FP64 solution (FFT + Thomas) all the same, because the FP64
+    residual decides convergence; its rate stays close to that of the rounded-beta
+    cycles (the two FP32 operators differ by two float32 ulps at most)."""
+    from oracle.multigrid import fp32_levels_from_rho
+    H, inp = c1_like(32, smear=1.0)
+    lv = fp32_levels_from_rho(H, inp.rho)
+    assert lv[0].bx.dtype == np.float32 and len(lv) == len(H.levels)
+    for a, b in zip(lv[1:], H.levels[1:]):
+        assert np.array_equal(a.bx, b.bx.astype(np.float32))
+    pm, hm = solve_mixed(H, inp.f, tol=1e-12, max_steps=60, lv32=lv)
+    assert hm[-1] <= 1e-12
+    assert relerr(pm, exact.solve_fft_z(H.fine, inp.f)) < 1e-9
+    _, hr = solve_mixed(H, inp.f, tol=1e-12, max_steps=60)
+    assert abs(len(hm) - len(hr)) <= 1

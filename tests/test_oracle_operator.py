@@ -114,6 +114,25 @@ def test_face_coefficients_from_density():
     assert 1.0 < w[0, 0, 1] < 1000.0
 
 
+def test_interface_face_is_inverse_of_mean_density():
+    """Reading C3: a face between water (rho = 1) and air (rho = 1e-3) takes 1/rho of the
+    mean density, 2/(1 + 1e-3) ~ 1.998, close to the water value: the heavy fluid limits
+    the flux.  The rejected reading (mean of 1/rho) would give (1 + 1000)/2 = 500.5.  A
+    z column water below air puts the interface on a z face; x and y faces stay inside one
+    fluid (1 and 1000)."""
+    N = 4
+    rho = np.ones((N, N, N))
+    rho[N // 2:] = 1e-3
+    bx, by, bz = face_coeffs_from_rho(rho, np.ones((N, N, N), np.uint8))
+    want = 2.0 / (1.0 + 1e-3)
+    assert np.all(bz[N // 2] == want)
+    assert abs(bz[N // 2, 0, 0] - 500.5) > 400.0
+    assert np.all(bz[1:N // 2] == 1.0) and np.allclose(bz[N // 2 + 1:], 1e3, rtol=1e-15, atol=0)
+    assert np.all(bz[0] == 0.0)
+    assert np.all(bx[:N // 2] == 1.0) and np.allclose(bx[N // 2:], 1e3, rtol=1e-15, atol=0)
+    assert np.array_equal(bx, by)
+
+
 def test_projection_removes_active_mean():
     mask = np.ones((4, 4, 4), bool)
     mask[0, 0, :2] = False

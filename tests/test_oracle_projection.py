@@ -52,3 +52,33 @@ def test_projection_makes_the_field_divergence_free():
     assert np.all(Un[0][~ox] == 0) and np.all(Un[2][~oz] == 0)
     # the source is compatible
     assert abs(fproject(f, H.fine.mask).sum() - f.sum()) < 1e-9 * np.abs(f).sum()
+
+
+def test_projection_is_idempotent():
+    """Projecting a projected field changes nothing: its divergence is zero, so the next
+    solve gives p = 0 (reading C21) and the projection returns the field as it is, the
+    closed faces still 0.  Wavy interface with the body at 16^3, exact solves."""
+    from oracle.multigrid import solve
+    inp = fields.wavy_body(16)
+    H = setup(*face_coeffs_from_rho(inp.rho, inp.mask), inp.mask, inp.h)
+    U, R = face_field(16, 127), face_field(16, 128)
+    dt = 0.01
+
+    def projected(V, R):
+        f = projection.divergence(V, H.fine, dt, R)
+        p = exact.solve_sparse(H.fine, f)
+        return projection.project(V, p, H.fine, dt, R)
+
+    U1 = projected(U, R)
+    f1 = projection.divergence(U1, H.fine, 1.0)
+    scale = max(np.abs(u).max() for u in U1)
+    p1, hist = solve(H, f1, tol=1e-12)
+    # what is left of the divergence is rounding: its solution is rounding-sized too
+    assert np.abs(p1).max() * np.abs(H.fine.bx).max() / H.fine.h <= 1e-9 * scale
+    U2 = projection.project(U1, p1, H.fine, 1.0)
+    for a, b in zip(U2, U1):
+        assert np.abs(a - b).max() <= 1e-9 * scale
+    # the projection of a field with no divergence and no forcing is the field itself
+    U3 = projection.project(U1, np.zeros_like(p1), H.fine, dt)
+    for a, b in zip(U3, U1):
+        assert np.array_equal(a, b)
