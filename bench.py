@@ -2,9 +2,13 @@
 
 One step = one pressure projection as the flow solver runs it at every Runge-Kutta
 stage: face products from the new density (on the device), hierarchy setup, and an
-FP64 multigrid solve from p = 0 to a relative residual of 1e-10.  The workload is
-the 256^3 wavy-interface field with the immersed ellipsoid body (density ratio 1000),
-inputs resident in HBM before timing starts.
+FP64 solve from p = 0 to a relative residual of 1e-10.  The default workload is the
+largest one that fits one GPU, the 1024^3 Stokes-crest field with the immersed
+ellipsoid (density ratio 1000; 1.07e9 cells), inputs resident in HBM before timing
+starts.  Its outer iteration is flexible CG with one V(2,2) cycle per step: plain
+V(2,2) cycling stalls near 2e-9 on this field (reported beside it).  The mixed-precision
+projection (FP32 cycles), the 512^3 and 256^3 workloads and the other legs of the path
+are extra keys of the same line.
 
 Prints one JSON line.  value = grid points x V-cycles / second over the timed steps.
 """
@@ -28,6 +32,10 @@ HBM_PEAK_GBS = 8000.0
 # the coarser grids.
 VCYCLE_SCALARS_F64 = 21.25 + 31.25 / 7
 VCYCLE_SCALARS_F32 = VCYCLE_SCALARS_F64
+# the same count with three face arrays on the finest grid too (31.25 x 8 / 7)
+VCYCLE_SCALARS_FACE = 31.25 * 8 / 7
+
+METRIC = "grid-pts/s per V-cycle + time-to-1e-10 residual (FP64 vs mixed), % HBM peak"
 
 
 def parse():
@@ -35,11 +43,16 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="c2", help="c1..c5 (default c2: 256^3 wavy interface + body)")
+    ap.add_argument("--config", default="c5",
+                    help="c1..c5 (default c5: 1024^3 Stokes crest + body, the largest single-GPU workload)")
     ap.add_argument("--n", type=int, default=None, help="override the grid size")
+    ap.add_argument("--outer", choices=("auto", "vcycle", "fcg"), default="auto",
+                    help="outer iteration of the timed projection (auto: flexible CG on c5, V-cycles otherwise)")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--max-cycles", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="leave out the 512^3 / 256^3 workloads and the 256^3 / 128^3 legs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device copy (HBM counter calibration) and exit")
     ap.add_argument("--oracle-timing", action="store_true",
@@ -54,6 +67,57 @@ def parse():
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def solve_timer(rho, mask, f, tol, max_cycles):
+    """Returns timed(mixed, krylov, steps, warmup): the mean time of `steps` projections
+    (setup from rho + solve from p = 0), with the last context, solution and history."""
+    import torch
+    from paper_1410_2240_amd import MG
+
+    def projection(mixed, krylov):
+        mg = MG.from_rho(rho, mask, mixed=mixed, krylov=krylov)
+        p, hist, st = mg.solve(f, tol=tol, max_cycles=max_cycles, raise_on_fail=False)
+        return mg, p, hist, st
+
+    def timed(mixed, krylov, steps, warmup):
+        for _ in range(warmup):
+            projection(mixed, krylov)
+        torch.cuda.synchronize()
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record()
+        cycles = 0
+        mg = p = None
+        for _ in range(steps):
+            del mg, p   # one hierarchy at a time: the previous step's is freed first
+            mg, p, hist, st = projection(mixed, krylov)
+            cycles += st["cycles"]
+        stop.record()
+        torch.cuda.synchronize()
+        return {"ms": start.elapsed_time(stop) / steps, "cycles": cycles / steps, "status": st["status"],
+                "final_relres": hist[-1], "mg": mg, "p": p, "hist": hist}
+
+    return timed
+
+
+def public(r):
+    return {k: v for k, v in r.items() if k not in ("mg", "p", "hist")}
+
+
+def vcycle_ms(mg, f, mask, dtype):
+    """Pure V-cycle time: 10 cycles with no residual checks, on a compatible f."""
+    import torch
+    fx = f if dtype == torch.float64 else ((f - f[mask.bool()].mean()) * mask).to(dtype)
+    p = torch.zeros_like(fx)
+    mg.vcycle(p, fx)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(10):
+        mg.vcycle(p, fx)
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / 10
 
 
 def main():
@@ -85,7 +149,6 @@ def main():
         return
 
     import fields
-    from paper_1410_2240_amd import MG
 
     t_gen = time.time()
     inp = fields.make(args.config, args.n)
@@ -95,45 +158,19 @@ def main():
     mask = torch.from_numpy(inp.mask).to(dev)
     f = torch.from_numpy(inp.f).to(dev)
     t_gen = time.time() - t_gen
-    log(f"inputs {inp.name} {N}^3 generated in {t_gen:.1f} s")
+    log(f"inputs {inp.name} {N}^3 generated and copied in {t_gen:.1f} s")
+    krylov = args.outer == "fcg" or (args.outer == "auto" and args.config == "c5")
+    outer = "flexible CG (FCG(1)), one V(2,2) RBGS cycle per step" if krylov else "V(2,2) RBGS cycles"
+    timed = solve_timer(rho, mask, f, args.tol, args.max_cycles)
 
-    def projection(mixed, krylov=False):
-        # face products from rho formed in the workspace, hierarchy, solve
-        mg = MG.from_rho(rho, mask, mixed=mixed, krylov=krylov)
-        p, hist, st = mg.solve(f, tol=args.tol, max_cycles=args.max_cycles, raise_on_fail=False)
-        return mg, p, hist, st
-
-    def timed(mixed, steps, warmup, krylov=False):
-        for _ in range(warmup):
-            projection(mixed, krylov)
-        torch.cuda.synchronize()
-        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        start.record()
-        cycles = 0
-        for _ in range(steps):
-            mg, p, hist, st = projection(mixed, krylov)
-            cycles += st["cycles"]
-        stop.record()
-        torch.cuda.synchronize()
-        return start.elapsed_time(stop) / steps, cycles / steps, mg, p, hist, st["status"]
-
-    # pure V-cycle time (10 cycles, no residual checks) in FP64 and FP32
-    def vcycle_ms(mg, dtype):
-        fx = f if dtype == torch.float64 else (f - f[mask.bool()].mean()).float() * mask
-        p = torch.zeros_like(fx)
-        mg.vcycle(p, fx)
-        torch.cuda.synchronize()
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record()
-        for _ in range(10):
-            mg.vcycle(p, fx)
-        b.record()
-        torch.cuda.synchronize()
-        return a.elapsed_time(b) / 10
-
-    ms64, cyc64, mg64, p64, hist64, st64 = timed(False, args.steps, args.warmup)
-    log(f"fp64 projection {ms64:.2f} ms, {cyc64:.0f} cycles, status {st64}")
-    vc64 = vcycle_ms(mg64, torch.float64)
+    # ---- the timed step: FP64 projection, exactly --steps of them after --warmup
+    torch.cuda.reset_peak_memory_stats()
+    r64 = timed(False, krylov, args.steps, args.warmup)
+    peak64 = torch.cuda.max_memory_allocated()
+    log(f"fp64 projection ({outer}) {r64['ms']:.2f} ms, {r64['cycles']:.0f} cycles, status {r64['status']}, "
+        f"relres {r64['final_relres']:.3e}")
+    mg64 = r64["mg"]
+    vc64 = vcycle_ms(mg64, f, mask, torch.float64)
 
     # dominant kernel: the finest-grid smoother, timed on the stream it runs on
     fz = torch.zeros_like(f)
@@ -141,7 +178,7 @@ def main():
     mg64.smooth(0, ps, fz, 2, 0)
     torch.cuda.synchronize()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    reps = 10
+    reps = 5 if N >= 1024 else 10
     a.record()
     for _ in range(reps):
         mg64.smooth(0, ps, fz, 2, 0)   # two one-pass sweeps, exactly as inside the V-cycle
@@ -150,30 +187,137 @@ def main():
     launch_ms = a.elapsed_time(b) / (2 * reps)
     # algorithmic bytes of one red-black sweep on the finest grid of a hierarchy built
     # from rho: p, f and the density form of the coefficients read, p written
-    half_bytes = n * 8 * 4
-    achieved = half_bytes / (launch_ms * 1e-3) / 1e9
-    del mg64, p64, fz, ps
+    sweep_bytes = n * 8 * 4
+    achieved = sweep_bytes / (launch_ms * 1e-3) / 1e9
+    del fz, ps
+    r64.pop("mg"), r64.pop("p")
+    del mg64
     torch.cuda.empty_cache()
 
-    msmx, cycmx, mgmx, pmx, histmx, stmx = timed(True, max(1, args.steps), 1)
-    log(f"mixed projection {msmx:.2f} ms, {cycmx:.0f} steps, status {stmx}")
-    vc32 = vcycle_ms(mgmx, torch.float32)
-    del mgmx, pmx
+    # ---- the mixed-precision projection (FP32 cycles inside FP64 refinement / FCG)
+    torch.cuda.reset_peak_memory_stats()
+    rmx = timed(True, krylov, max(1, args.steps // 4), 1)
+    peakmx = torch.cuda.max_memory_allocated()
+    log(f"mixed projection ({outer}) {rmx['ms']:.2f} ms, {rmx['cycles']:.0f} steps, status {rmx['status']}, "
+        f"relres {rmx['final_relres']:.3e}")
+    vc32 = vcycle_ms(rmx["mg"], f, mask, torch.float32)
+    rmx.pop("mg"), rmx.pop("p")
     torch.cuda.empty_cache()
 
-    # flexible CG outer iteration (one V-cycle per step), FP64 and FP32 preconditioner
-    kr = {}
+    # ---- the other outer iteration on the same field, once each (plain V(2,2) cycling is
+    # the paper's method; on the crest field it stalls and ends in MG_ENOCONV)
+    other = {}
     for mixed in (False, True):
-        ms, cyc, mgk, pk, hist, st = timed(mixed, max(1, args.steps), 1, krylov=True)
-        kr["mixed" if mixed else "fp64"] = {"ms": ms, "steps": cyc, "final_relres": hist[-1], "status": st}
-        log(f"fcg {'mixed' if mixed else 'fp64'} {ms:.2f} ms, {cyc:.0f} steps, status {st}")
-        del mgk, pk
+        cap = 100 if krylov else args.max_cycles
+        ro = solve_timer(rho, mask, f, args.tol, cap)(mixed, not krylov, 1, 0)
+        ro.pop("mg"), ro.pop("p"), ro.pop("hist")
+        ro["max_cycles"] = cap
+        ro["note"] = "one run, its first allocation of the workspace included"
+        other["mixed" if mixed else "fp64"] = ro
+        log(f"{'V-cycles' if krylov else 'flexible CG'} {'mixed' if mixed else 'fp64'}: {ro}")
         torch.cuda.empty_cache()
+    r64.pop("hist"), rmx.pop("hist")
+    del rho, mask, f
+    torch.cuda.empty_cache()
 
-    # coarsening ablation (section 3.1): face products moved as one unit against density
-    # restricted cell centre to cell centre, both as flexible-CG preconditioners, and the
-    # plain V-cycle with density coarsening (which the paper reports as slower)
-    abl = {}
+    legs = {}
+    if not args.no_legs and args.config == "c5":
+        legs["c3_flat_smear1_512"] = config_leg("c3", 512, args)
+        legs["c2_wavy_body_256"] = config_leg("c2", 256, args)
+    if not args.no_legs:
+        legs["coarsening_ablation"] = coarsening_leg(256, args)
+        legs["cut_cells"] = cut_cell_leg(256, args)
+        legs["differentiation"] = differentiation_leg(args)
+        legs["rk2_projection"] = rk2_leg(256, args)
+    traffic = recorded_traffic(inp.name, N)
+    scalars_f64 = VCYCLE_SCALARS_F64
+    out = {
+        "metric": METRIC,
+        "value_definition": f"grid points x V-cycles / time of the FP64 projection (setup from rho + solve to "
+                            f"{args.tol:g} from p = 0, outer iteration: {outer}); time_to_tol_ms gives FP64 and "
+                            f"mixed, roofline and vcycle_roofline_frac the fraction of HBM peak",
+        "value": n * r64["cycles"] / (r64["ms"] * 1e-3),
+        "unit": "grid-pts/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": r64["ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": inp.name, "N": N, "cells": n, "tol": args.tol, "outer": outer,
+                   "cycle": "V(2,2) RBGS", "density_ratio": 1000},
+        "time_to_tol_ms": {"fp64": r64["ms"], "mixed": rmx["ms"], "mixed_speedup": r64["ms"] / rmx["ms"]},
+        "cycles_to_tol": {"fp64": r64["cycles"], "mixed": rmx["cycles"]},
+        "final_relres": {"fp64": r64["final_relres"], "mixed": rmx["final_relres"]},
+        "status": {"fp64": r64["status"], "mixed": rmx["status"]},
+        "mixed_steps_timed": max(1, args.steps // 4),
+        ("plain_vcycles" if krylov else "krylov_fcg"): other,
+        "peak_memory_bytes": {"fp64": peak64, "mixed": peakmx},
+        "vcycle_ms": {"fp64": vc64, "fp32": vc32},
+        "vcycle_pts_per_s": {"fp64": n / (vc64 * 1e-3), "fp32": n / (vc32 * 1e-3)},
+        # algorithmic scalars per finest cell per V(2,2) cycle of the design that runs
+        # (density form on the finest grid), and against the face-array count
+        "vcycle_roofline_frac": {"fp64": scalars_f64 * 8 * n / (vc64 * 1e-3) / (HBM_PEAK_GBS * 1e9),
+                                 "fp32": VCYCLE_SCALARS_F32 * 4 * n / (vc32 * 1e-3) / (HBM_PEAK_GBS * 1e9),
+                                 "fp64_face_array_count": VCYCLE_SCALARS_FACE * 8 * n / (vc64 * 1e-3)
+                                 / (HBM_PEAK_GBS * 1e9),
+                                 "fp32_face_array_count": VCYCLE_SCALARS_FACE * 4 * n / (vc32 * 1e-3)
+                                 / (HBM_PEAK_GBS * 1e9)},
+        "roofline": {"bound": "hbm", "kernel": "rbgs_fused (finest grid, FP64 density form, one red-black sweep)",
+                     "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "launch_ms": launch_ms, "bytes_per_launch": sweep_bytes},
+        "input_gen_s": t_gen,
+        **legs,
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle")
+        out["cpu_baseline"] = cpu_baseline(inp)
+    print(json.dumps(out), flush=True)
+
+
+def config_leg(name, N, args):
+    """Another workload at its own size: FP64 against mixed, plain V-cycles and flexible
+    CG, each the mean of three projections (setup + solve to tol) after one warm-up."""
+    import torch
+    import fields
+    t0 = time.time()
+    inp = fields.make(name, N)
+    rho = torch.from_numpy(inp.rho).cuda()
+    mask = torch.from_numpy(inp.mask).cuda()
+    f = torch.from_numpy(inp.f).cuda()
+    out = {"workload": inp.name, "N": N, "input_gen_s": time.time() - t0}
+    del inp
+    timed = solve_timer(rho, mask, f, args.tol, args.max_cycles)
+    for krylov in (False, True):
+        row = {}
+        for mixed in (False, True):
+            r = timed(mixed, krylov, 3, 1)
+            if not krylov:
+                r[("fp32" if mixed else "fp64") + "_vcycle_ms"] = vcycle_ms(r["mg"], f, mask,
+                                                                            torch.float32 if mixed else torch.float64)
+            row["mixed" if mixed else "fp64"] = public(r)
+            del r
+            torch.cuda.empty_cache()
+        row["mixed_speedup"] = row["fp64"]["ms"] / row["mixed"]["ms"]
+        out["flexible_cg" if krylov else "vcycles"] = row
+    log(f"{out['workload']}: {out}")
+    del rho, mask, f
+    torch.cuda.empty_cache()
+    return out
+
+
+def coarsening_leg(N, args):
+    """Coarsening ablation (section 3.1) on the wavy interface + body field: face
+    products moved as one unit against density restricted cell centre to cell centre,
+    both as flexible-CG preconditioners, and the plain V-cycle with each (the paper
+    reports density restriction as the slower one)."""
+    import torch
+    import fields
+    from paper_1410_2240_amd import MG
+    inp = fields.make("c2", N)
+    rho = torch.from_numpy(inp.rho).cuda()
+    mask = torch.from_numpy(inp.mask).cuda()
+    f = torch.from_numpy(inp.f).cuda()
+    abl = {"workload": f"{inp.name}_{N}"}
     for mode in ("face", "density"):
         torch.cuda.synchronize()
         t0 = time.time()
@@ -188,48 +332,7 @@ def main():
         del mgp
         torch.cuda.empty_cache()
     log(f"coarsening ablation {abl}")
-    cut = cut_cell_leg(N, args) if args.config == "c2" else None
-    diff = differentiation_leg(args) if args.config == "c2" else None
-    rk2 = rk2_leg(N, args) if args.config == "c2" else None
-    traffic = recorded_traffic(inp.name, N)
-    out = {
-        "metric": "grid-pts/s per V-cycle + time-to-1e-10 residual (FP64 vs mixed), % HBM peak",
-        "value_definition": "grid points x V-cycles / time of the FP64 projection (setup from rho + solve to "
-                            "1e-10 from p = 0); time_to_tol_ms gives FP64 and mixed, roofline and "
-                            "vcycle_roofline_frac the fraction of HBM peak",
-        "value": n * cyc64 / (ms64 * 1e-3),
-        "unit": "grid-pts/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms64,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
-        "config": {"workload": inp.name, "N": N, "cells": n, "tol": args.tol, "cycle": "V(2,2) RBGS",
-                   "density_ratio": 1000},
-        "time_to_tol_ms": {"fp64": ms64, "mixed": msmx, "mixed_speedup": ms64 / msmx},
-        "cycles_to_tol": {"fp64": cyc64, "mixed_ir_steps": cycmx},
-        "final_relres": {"fp64": hist64[-1], "mixed": histmx[-1]},
-        "status": {"fp64": st64, "mixed": stmx},
-        "krylov_fcg": kr,
-        "coarsening_ablation": abl,
-        "cut_cells": cut,
-        "differentiation": diff,
-        "rk2_projection": rk2,
-        "vcycle_ms": {"fp64": vc64, "fp32": vc32},
-        "vcycle_pts_per_s": {"fp64": n / (vc64 * 1e-3), "fp32": n / (vc32 * 1e-3)},
-        # algorithmic scalars per finest cell per V(2,2) cycle: the FP64 finest grid reads
-        # the density form (4 sweeps x 4 + 3.125 + 2.125), FP32 grids the face arrays
-        "vcycle_roofline_frac": {"fp64": VCYCLE_SCALARS_F64 * 8 * n / (vc64 * 1e-3) / (HBM_PEAK_GBS * 1e9),
-                                 "fp32": VCYCLE_SCALARS_F32 * 4 * n / (vc32 * 1e-3) / (HBM_PEAK_GBS * 1e9)},
-        "roofline": {"bound": "hbm", "kernel": "rbgs_fused (finest grid, FP64 density form, one red-black sweep)",
-                     "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "launch_ms": launch_ms, "bytes_per_launch": half_bytes},
-        "input_gen_s": t_gen,
-    }
-    if not args.no_cpu_baseline:
-        log("timing the CPU oracle")
-        out["cpu_baseline"] = cpu_baseline(inp)
-    print(json.dumps(out), flush=True)
+    return abl
 
 
 def cut_cell_leg(N, args):
@@ -476,31 +579,59 @@ def coarsening_sweep(args):
     return out
 
 
+TRAFFIC_KERNEL = "k_rbgs_fused<double, 128, 16, true, false>"
+
+
+def kernel_source_hash():
+    """SHA-256 over the sources the one-pass sweep is compiled from and the hipcc flags:
+    recorded counter traffic is valid only for the build it was taken on."""
+    import hashlib
+    from paper_1410_2240_amd import build as _build
+    hsh = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES:
+        hsh.update(rel.encode())
+        hsh.update(open(os.path.join(ROOT, rel), "rb").read())
+    hsh.update(" ".join(_build.HIPCC_FLAGS).encode())
+    return hsh.hexdigest()
+
+
+TRAFFIC_SOURCES = ("paper_1410_2240_amd/csrc/mg_fused.hip", "paper_1410_2240_amd/csrc/mg_buffer.h",
+                   "paper_1410_2240_amd/csrc/mg_kernels.h")
+
+
 def recorded_traffic(workload, N):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter
     runs (scaled FETCH_SIZE + WRITE_SIZE), or None when they were taken on another
-    workload or the kernel source has changed since."""
-    import hashlib
+    workload or size, or the kernel's sources or build flags have changed since."""
     try:
-        rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))["k_rbgs_fused<double, 128, 16, true, false>"]
+        rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))[TRAFFIC_KERNEL]
     except (OSError, KeyError, ValueError):
         return None
-    src = open(os.path.join(ROOT, rec["source"]), "rb").read()
-    if hashlib.sha256(src).hexdigest() != rec["source_sha256"] or rec["workload"] != workload or rec["N"] != N:
+    if rec.get("build_sha256") != kernel_source_hash() or rec["workload"] != workload or rec["N"] != N:
         return None
     return rec["traffic_bytes_per_launch"]
 
 
 def cpu_baseline(inp):
-    """The oracle's FP64 V-cycle on the same workload, timed on this host."""
+    """The oracle on this host's cores, on a bounded sample of the same workload.
+
+    value: the oracle's FP64 V(2,2) cycle in grid points per second, on the same field
+    recipe at the largest size whose cycle takes seconds (256^3 for the 1024^3 field: one
+    oracle cycle at 1024^3 would take minutes).  Beside it, at the full size, the oracle's
+    FP64 residual r = P f - A p (the part of a cycle it can run there) over a 64-plane
+    slab, in grid points per second."""
     import numpy as np
 
+    import fields
     from oracle import multigrid as omg
-    from oracle.operator import face_coeffs_from_rho, project
+    from oracle.operator import Level, apply, diagonal, face_coeffs_from_rho, project
+    name = next(k for k in fields.WORKLOADS if inp.name.startswith(k + "_"))
+    Ns = min(inp.N, 256)
+    small = inp if Ns == inp.N else fields.make(name, Ns)
     t0 = time.time()
-    H = omg.setup(*face_coeffs_from_rho(inp.rho, inp.mask), inp.mask, inp.h)
+    H = omg.setup(*face_coeffs_from_rho(small.rho, small.mask), small.mask, small.h)
     t_setup = time.time() - t0
-    fh = project(inp.f, H.fine.mask)
+    fh = project(small.f, H.fine.mask)
     p = np.zeros_like(fh)
     cycles = 0
     t0 = time.time()
@@ -508,10 +639,25 @@ def cpu_baseline(inp):
         p = omg.vcycle(H, p, fh)
         cycles += 1
     dt = (time.time() - t0) / cycles
-    return {"value": inp.n / dt, "unit": "grid-pts/s", "cores": 1, "kind": "oracle",
-            "sample": f"{cycles} FP64 V(2,2) cycles of the numpy oracle on the same {inp.N}^3 workload "
-                      f"(setup {t_setup:.1f} s excluded); numpy elementwise kernels are single-threaded",
-            "host_cpus": os.cpu_count()}
+    del H, fh, p
+    out = {"value": small.n / dt, "unit": "grid-pts/s", "cores": 1, "kind": "oracle",
+           "sample": f"{cycles} FP64 V(2,2) cycles of the numpy oracle on the {name} recipe at {Ns}^3 "
+                     f"(setup {t_setup:.1f} s excluded); numpy elementwise kernels are single-threaded",
+           "host_cpus": os.cpu_count()}
+    if inp.N > Ns:
+        # the residual of a random p over planes 448..511 of the full grid (faces formed
+        # from the planes either side, as on the whole grid)
+        k0, k1 = inp.N // 2 - 64, inp.N // 2
+        t0 = time.time()
+        m = inp.mask[k0 - 1:k1 + 1].astype(bool)
+        lev = Level(*face_coeffs_from_rho(inp.rho[k0 - 1:k1 + 1], m), m, inp.h)
+        lev.mask = m & (diagonal(lev) > 0)
+        pr = np.random.default_rng(3).standard_normal(m.shape)
+        r = np.where(lev.mask, inp.f[k0 - 1:k1 + 1] - apply(pr, lev), 0.0)[1:-1]
+        t_res = time.time() - t0
+        out["full_size_residual"] = {"pts_per_s": (k1 - k0) * inp.N * inp.N / t_res, "planes": k1 - k0,
+                                     "N": inp.N, "seconds": t_res, "norm2": float(np.sum(r * r))}
+    return out
 
 
 def oracle_timing():

@@ -35,6 +35,8 @@ from __future__ import annotations
 import dataclasses
 import hashlib
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
@@ -48,6 +50,25 @@ BODY_SEMI_AXES = (0.3, 0.08, 0.06)
 
 def rng(field: int, index: int = 0) -> np.random.Generator:
     return np.random.default_rng([SEED, field, index])
+
+
+def _workers() -> int:
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def _over_slabs(N: int, fn, min_n: int = 128) -> None:
+    """Run fn(k0, k1) over contiguous z ranges covering 0..N-1, on a thread pool for
+    large grids (numpy releases the GIL on slab-sized arrays).  Every draw and every
+    value of a slab depends on its index only, so the result is the same bits whatever
+    the split."""
+    W = _workers() if N >= min_n else 1
+    if W == 1:
+        fn(0, N)
+        return
+    step = -(-N // (4 * W))
+    with ThreadPoolExecutor(W) as ex:
+        for fut in [ex.submit(fn, k0, min(N, k0 + step)) for k0 in range(0, N, step)]:
+            fut.result()
 
 
 def centres(N: int) -> np.ndarray:
@@ -166,37 +187,48 @@ def divergence_rhs(mask: np.ndarray, field: int = F_VELOCITY, index0: int = 0,
     inv_h = float(N)
     f = np.empty((N, N, N)) if out is None else out
     m = mask.astype(bool)
-    u_prev = None
-    u_cur = _velocity_slab(field, index0, N)
-    for k in range(N):
-        u_next = _velocity_slab(field, index0 + k + 1, N) if k + 1 < N else None
-        mk = m[k]
-        ux, uy, uz = u_cur
-        # x faces: low face of cell i sits between i-1 (periodic) and i
-        ox = mk & np.roll(mk, 1, axis=1)
-        Ux = np.where(ox, 0.5 * (ux + np.roll(ux, 1, axis=1)), 0.0)
-        oy = mk & np.roll(mk, 1, axis=0)
-        Uy = np.where(oy, 0.5 * (uy + np.roll(uy, 1, axis=0)), 0.0)
-        div = (np.roll(Ux, -1, axis=1) - Ux) + (np.roll(Uy, -1, axis=0) - Uy)
-        if k > 0:   # face between k-1 and k
-            Uz_lo = np.where(mk & m[k - 1], 0.5 * (uz + u_prev[2]), 0.0)
-        else:
-            Uz_lo = 0.0
-        if k + 1 < N:   # face between k and k+1
-            Uz_hi = np.where(mk & m[k + 1], 0.5 * (uz + u_next[2]), 0.0)
-        else:
-            Uz_hi = 0.0
-        div = div + (Uz_hi - Uz_lo)
-        f[k] = np.where(mk, div * inv_h, 0.0)
-        u_prev, u_cur = u_cur, u_next
+    sums = np.zeros(N)
+    counts = np.zeros(N, dtype=np.int64)
+
+    def slabs(k0, k1):
+        u_prev = _velocity_slab(field, index0 + k0 - 1, N) if k0 > 0 else None
+        u_cur = _velocity_slab(field, index0 + k0, N)
+        for k in range(k0, k1):
+            u_next = _velocity_slab(field, index0 + k + 1, N) if k + 1 < N else None
+            mk = m[k]
+            ux, uy, uz = u_cur
+            # x faces: low face of cell i sits between i-1 (periodic) and i
+            ox = mk & np.roll(mk, 1, axis=1)
+            Ux = np.where(ox, 0.5 * (ux + np.roll(ux, 1, axis=1)), 0.0)
+            oy = mk & np.roll(mk, 1, axis=0)
+            Uy = np.where(oy, 0.5 * (uy + np.roll(uy, 1, axis=0)), 0.0)
+            div = (np.roll(Ux, -1, axis=1) - Ux) + (np.roll(Uy, -1, axis=0) - Uy)
+            if k > 0:   # face between k-1 and k
+                Uz_lo = np.where(mk & m[k - 1], 0.5 * (uz + u_prev[2]), 0.0)
+            else:
+                Uz_lo = 0.0
+            if k + 1 < N:   # face between k and k+1
+                Uz_hi = np.where(mk & m[k + 1], 0.5 * (uz + u_next[2]), 0.0)
+            else:
+                Uz_hi = 0.0
+            div = div + (Uz_hi - Uz_lo)
+            f[k] = np.where(mk, div * inv_h, 0.0)
+            sums[k] = float(f[k][mk].sum())
+            counts[k] = int(mk.sum())
+            u_prev, u_cur = u_cur, u_next
+
+    _over_slabs(N, slabs)
+    # the fluid mean, summed slab by slab in z order
     total = 0.0
-    count = 0
     for k in range(N):
-        total += float(f[k][m[k]].sum())
-        count += int(m[k].sum())
-    mean = total / count
-    for k in range(N):
-        f[k] = np.where(m[k], f[k] - mean, 0.0)
+        total += float(sums[k])
+    mean = total / int(counts.sum())
+
+    def remove(k0, k1):
+        for k in range(k0, k1):
+            f[k] = np.where(m[k], f[k] - mean, 0.0)
+
+    _over_slabs(N, remove)
     return f
 
 
@@ -233,12 +265,16 @@ def wavy_body(N: int, name: str = "wavy_body") -> Inputs:
     rho = np.empty((N, N, N))
     mask = np.empty((N, N, N), dtype=np.uint8)
     h = 1.0 / N
-    for k in range(N):
-        z = (k + 0.5) * h
-        phi = 0.5 * (1.0 - np.tanh((z - zs) / (2.0 * h)))
-        mk = body_mask_slab(N, k, (0.5, 0.5, zc))
-        mask[k] = mk
-        rho[k] = np.where(mk == 1, density_from_phi(phi), 1.0)
+
+    def slabs(k0, k1):
+        for k in range(k0, k1):
+            z = (k + 0.5) * h
+            phi = 0.5 * (1.0 - np.tanh((z - zs) / (2.0 * h)))
+            mk = body_mask_slab(N, k, (0.5, 0.5, zc))
+            mask[k] = mk
+            rho[k] = np.where(mk == 1, density_from_phi(phi), 1.0)
+
+    _over_slabs(N, slabs)
     return Inputs(name, N, rho, mask, divergence_rhs(mask))
 
 
@@ -294,12 +330,16 @@ def stokes_crest(N: int, name: str = "stokes_crest") -> Inputs:
     zc = float(stokes_eta(0.5))
     rho = np.empty((N, N, N))
     mask = np.empty((N, N, N), dtype=np.uint8)
-    for k in range(N):
-        d = _stokes_distance_slab(N, k, feat)
-        phi = 0.5 * (1.0 - np.tanh(d / h))
-        mk = body_mask_slab(N, k, (0.5, 0.5, zc))
-        mask[k] = mk
-        rho[k] = np.where(mk == 1, density_from_phi(phi), 1.0)
+
+    def slabs(k0, k1):
+        for k in range(k0, k1):
+            d = _stokes_distance_slab(N, k, feat)
+            phi = 0.5 * (1.0 - np.tanh(d / h))
+            mk = body_mask_slab(N, k, (0.5, 0.5, zc))
+            mask[k] = mk
+            rho[k] = np.where(mk == 1, density_from_phi(phi), 1.0)
+
+    _over_slabs(N, slabs)
     return Inputs(name, N, rho, mask, divergence_rhs(mask))
 
 

@@ -52,16 +52,19 @@ def test_coefficients_and_moves_match_oracle(N):
     rho, psi = fields.wavy_cut(N)
     geo = cut_cells(dev(psi), 8)
     bx, by, bz, mask = (host(t) for t in cut_coeffs(dev(rho), *geo))
-    ax, ay, az, vol, mt = (host(t) for t in geo)
-    lev = cc.cut_coeffs(rho, ax, ay, az, vol, mt.astype(np.int64), 1.0 / N)
+    # the oracle's geometry from psi itself (not from the GPU's fractions and map)
+    ax, ay, az = cc.face_fractions(psi, 8)
+    vol = cc.volume_fractions(psi, 8)
+    mt = cc.merge_targets(psi, vol)
+    lev = cc.cut_coeffs(rho, ax, ay, az, vol, mt, 1.0 / N)
     assert np.array_equal(mask.astype(bool), lev.mask)
     for g, w in ((bx, lev.bx), (by, lev.by), (bz, lev.bz)):
         assert maxrel(g, w) <= 1e-15
     g = np.random.default_rng(11)
     f = g.standard_normal((N, N, N))
-    assert np.array_equal(host(merge_rhs(geo[4], dev(f))), cc.merge_rhs(f, mt.astype(np.int64)))
+    assert np.array_equal(host(merge_rhs(geo[4], dev(f))), cc.merge_rhs(f, mt))
     p = g.standard_normal((N, N, N))
-    assert np.array_equal(host(merge_fill(geo[4], dev(p))), cc.merge_fill(p, mt.astype(np.int64)))
+    assert np.array_equal(host(merge_fill(geo[4], dev(p))), cc.merge_fill(p, mt))
 
 
 @pytest.mark.parametrize("krylov", [False, True])
@@ -80,10 +83,13 @@ def test_cut_cell_solve_matches_sparse_direct(krylov):
     f = merge_rhs(geo[4], dev(f0))
     p, hist, st = mg.solve(f, tol=1e-12, max_cycles=200)
     merge_fill(geo[4], p)
-    mt = host(geo[4]).astype(np.int64)
-    lev = cc.cut_coeffs(rho, *(host(t) for t in geo[:4]), mt, 1.0 / N)
+    # the oracle's merged system from psi itself
+    ax, ay, az = cc.face_fractions(psi, 8)
+    vol = cc.volume_fractions(psi, 8)
+    mt = cc.merge_targets(psi, vol)
+    lev = cc.cut_coeffs(rho, ax, ay, az, vol, mt, 1.0 / N)
     lev = omg.setup(lev.bx, lev.by, lev.bz, lev.mask, lev.h).fine   # drops cells without an open face
     fo = cc.merge_rhs(f0, mt)
     want = cc.merge_fill(exact.solve_sparse(lev, project(fo, lev.mask)), mt)
-    live = (host(geo[3]) > 0)
+    live = vol > 0
     assert relerr(np.where(live, host(p), 0.0), np.where(live, want, 0.0)) <= 1e-9
