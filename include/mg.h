@@ -187,6 +187,26 @@ int mg_solve(mg_ctx* ctx, const double* f, double* p, int batch, double tol, int
 size_t mg_lane_workspace_size(const int dims[3], int flags);
 int mg_add_lanes(mg_ctx* ctx, void* workspace, size_t ws_bytes, int lanes);
 
+/*
+ * mg_solve for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same solve, bit
+ * for bit, with every array it writes besides p (the right-hand sides, corrections and
+ * second buffers of the grids, the flexible-CG vectors, reduction partials and device
+ * scalars) in a static device array of the library, 32 MiB per GPU, instead of the
+ * context's workspace.  The caller passes f, p, hist, n_hist and stats as for mg_solve;
+ * the batch is solved item after item on the context's stream (its lanes are not used).
+ * The call makes no allocation on the device (no hipMalloc, hipFree or allocating
+ * library routine).  Limit: the scratch of one solve must fit the 32 MiB, which holds
+ * grids up to 128^3 in FP64 and up to 64^3 with MG_MIXED or MG_KRYLOV; a larger context
+ * gets MG_EINVAL with the sizes in the message.  Every call on one GPU shares that GPU's
+ * array, which keeps the last call's contents (a solve initialises whatever it reads):
+ * calls that overlap on one GPU - from two host threads, or on two streams without
+ * ordering between them - race and give wrong results.  Errors as mg_solve, plus
+ * MG_EINVAL if the current device is not that of the context's stream.
+ */
+int mg_solve_static(mg_ctx* ctx, const double* f, double* p, int batch, double tol, int max_cycles,
+                    double* hist, int* n_hist, mg_stats* stats);
+
 /* Ap_b = A p_b on the finest grid (0 in the body). */
 int mg_apply(mg_ctx* ctx, const double* p, double* Ap, int batch);
 

@@ -44,6 +44,7 @@ SIGNATURES = {
     "mg_setup_from_rho": (_I, [ctypes.POINTER(_P), _P, ctypes.c_size_t, _P, _P, _DIMS, _D, _I, _P]),
     "mg_set_stream": (_I, [_P, _P]),
     "mg_solve": (_I, [_P, _P, _P, _I, _D, _I, ctypes.POINTER(_D), ctypes.POINTER(_I), ctypes.POINTER(MgStats)]),
+    "mg_solve_static": (_I, [_P, _P, _P, _I, _D, _I, ctypes.POINTER(_D), ctypes.POINTER(_I), ctypes.POINTER(MgStats)]),
     "mg_lane_workspace_size": (ctypes.c_size_t, [_DIMS, _I]),
     "mg_add_lanes": (_I, [_P, _P, ctypes.c_size_t, _I]),
     "mg_apply": (_I, [_P, _P, _P, _I]),

@@ -12,6 +12,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <type_traits>
@@ -768,6 +769,88 @@ int solve_lanes(mg_ctx* ctx, const double* f, double* p, int batch, double tol, 
 
 }  // namespace
 
+// ---------------------------------------------------------------- a solve that allocates nothing
+
+// mg_solve_static keeps the arrays one solve writes (the layout of one lane,
+// build_lane_plan) in this file-scope device array instead of the context's workspace.
+// Every GPU the library runs on holds its own copy until the process ends.  In host
+// code the name `scratch` is a host-side stand-in, not the device memory: the device
+// address comes from hipGetSymbolAddress, once per device with that device current,
+// and only that address is handed to kernels.
+constexpr size_t kStaticScratchBytes = static_cast<size_t>(32) << 20;
+constexpr int kMaxStaticDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mutex;
+unsigned char* g_scratch_ptr[kMaxStaticDevices] = {};
+
+int static_scratch(int device, unsigned char** out) {
+  if (device < 0 || device >= kMaxStaticDevices) return fail(MG_EINVAL, "device %d out of range", device);
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(MG_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", device, hipGetErrorString(e));
+    g_scratch_ptr[device] = static_cast<unsigned char*>(ptr);
+  }
+  *out = g_scratch_ptr[device];
+  return MG_OK;
+}
+
+// Points a context's per-solve arrays into another block laid out by build_lane_plan
+// and puts the context's own back on destruction (no allocation either way).
+class ScratchSwap {
+ public:
+  ScratchSwap(mg_ctx* c, unsigned char* base, const mg::Plan& lp) : c_(c) {
+    for (int l = 0; l < c->L; ++l) saved_[l] = c->lv[l];
+    partials_ = c->partials;
+    scal_ = c->scal;
+    kr_ = c->kr;
+    kz_ = c->kz;
+    kd_ = c->kd;
+    kw_ = c->kw;
+    for (int l = 0; l < c->L; ++l) {
+      Level& a = c->lv[l];
+      const mg::LevelPlan& q = lp.lv[l];
+      a.f = l > 0 ? at<double>(base, q.f) : a.f;
+      a.e = l > 0 ? at<double>(base, q.e) : a.e;
+      a.t = at<double>(base, q.t);
+      if (c->flags & MG_MIXED) {
+        a.f32 = at<float>(base, q.f32);
+        a.e32 = at<float>(base, q.e32);
+        a.t32 = at<float>(base, q.t32);
+      }
+    }
+    c->partials = at<double>(base, lp.partials);
+    c->scal = at<double>(base, lp.scalars);
+    c->kr = at<double>(base, lp.kr);
+    c->kz = at<double>(base, lp.kz);
+    c->kd = at<double>(base, lp.kd);
+    c->kw = at<double>(base, lp.kw);
+  }
+  ~ScratchSwap() {
+    for (int l = 0; l < c_->L; ++l) c_->lv[l] = saved_[l];
+    c_->partials = partials_;
+    c_->scal = scal_;
+    c_->kr = kr_;
+    c_->kz = kz_;
+    c_->kd = kd_;
+    c_->kw = kw_;
+  }
+  ScratchSwap(const ScratchSwap&) = delete;
+  ScratchSwap& operator=(const ScratchSwap&) = delete;
+
+ private:
+  mg_ctx* c_;
+  Level saved_[mg::kMaxLevels];
+  double *partials_, *scal_, *kr_, *kz_, *kd_, *kw_;
+};
+
+}  // namespace
+
 extern "C" {
 
 const char* mg_last_error(void) { return g_error.c_str(); }
@@ -890,6 +973,68 @@ int mg_solve(mg_ctx* ctx, const double* f, double* p, int batch, double tol, int
     }
   }
   if (first_bad >= 0) g_error = res[first_bad].err;
+  if (stats) {
+    stats->cycles = total_cycles;
+    stats->levels = ctx->L;
+    stats->active_cells = ctx->active;
+    stats->dropped_cells = ctx->dropped;
+    stats->removed_mean = removed;
+    stats->final_relres = worst;
+    stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    stats->ws_bytes = ctx->plan.total;
+  }
+  return status;
+}
+
+int mg_solve_static(mg_ctx* ctx, const double* f, double* p, int batch, double tol, int max_cycles, double* hist,
+                    int* n_hist, mg_stats* stats) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!ctx) return fail(MG_EINVAL, "null context");
+  if (!f || !p) return fail(MG_EINVAL, "null array pointer");
+  if (batch < 1) return fail(MG_EINVAL, "batch must be >= 1");
+  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(MG_EINVAL, "tol must be positive and finite");
+  if (max_cycles < 0) return fail(MG_EINVAL, "max_cycles must be >= 0");
+  mg::Plan lp;
+  if (mg::build_lane_plan(ctx->lv[0].n, ctx->flags, &lp) != 0) return fail(MG_EINVAL, "unsupported grid");
+  if (lp.total > kStaticScratchBytes)
+    return fail(MG_EINVAL,
+                "mg_solve_static: a %d^3 solve with flags %d needs %zu bytes of scratch, more than the %zu-byte "
+                "static scratch (up to 128^3 in FP64, 64^3 with MG_MIXED or MG_KRYLOV); use mg_solve",
+                ctx->lv[0].n, ctx->flags, lp.total, kStaticScratchBytes);
+  int device = 0;
+  MG_HIP(hipGetDevice(&device));
+  if (ctx->stream) {
+    hipDevice_t sdev = 0;
+    MG_HIP(hipStreamGetDevice(ctx->stream, &sdev));
+    if (static_cast<int>(sdev) != device)
+      return fail(MG_EINVAL, "the context's stream is on device %d, the current device is %d", static_cast<int>(sdev),
+                  device);
+  }
+  unsigned char* base = nullptr;
+  MG_TRY(static_scratch(device, &base));
+  const long long n3 = cells(ctx->lv[0]);
+  int status = MG_OK, total_cycles = 0;
+  double removed = 0.0, worst = 0.0;
+  char first_msg[512] = "";
+  {
+    ScratchSwap swap(ctx, base, lp);
+    for (int b = 0; b < batch; ++b) {
+      double* hb = hist ? hist + static_cast<long long>(b) * (max_cycles + 1) : nullptr;
+      int nh = 0, cyc = 0;
+      double rm = 0.0, fr = 0.0;
+      const int rc = solve_one(ctx, f + b * n3, p + b * n3, tol, max_cycles, hb, &nh, &rm, &fr, &cyc);
+      if (n_hist) n_hist[b] = nh;
+      if (rc == MG_EINVAL || rc == MG_EHIP) return rc;   // g_error holds the message
+      total_cycles += cyc;
+      removed = rm;
+      worst = std::fmax(worst, fr);
+      if (rc != MG_OK && status == MG_OK) {
+        status = rc;
+        std::snprintf(first_msg, sizeof first_msg, "%s", g_error.c_str());
+      }
+    }
+  }
+  if (status != MG_OK) g_error = first_msg;
   if (stats) {
     stats->cycles = total_cycles;
     stats->levels = ctx->L;

@@ -133,10 +133,14 @@ class MG:
 
     # ---------------------------------------------------------------- solve
 
-    def solve(self, f, p=None, tol: float = 1e-10, max_cycles: int = 100, raise_on_fail: bool = True):
+    def solve(self, f, p=None, tol: float = 1e-10, max_cycles: int = 100, raise_on_fail: bool = True,
+              static_scratch: bool = False):
         """Solve A p = P f (batched over a leading axis).  Returns (p, hist, stats).
 
         hist is a list (per batch item) of relative residuals, the first for the guess.
+        static_scratch: call mg_solve_static, whose scratch is the library's static
+        device array instead of this hierarchy's workspace (grids up to 128^3 in FP64,
+        64^3 mixed or flexible CG).
         """
         self._sync_stream()
         batched = f.dim() == 4
@@ -146,11 +150,12 @@ class MG:
         hist = np.zeros(B * (max_cycles + 1), dtype=np.float64)
         n_hist = (ctypes.c_int * B)()
         stats = MgStats()
-        rc = _lib.load().mg_solve(self._ctx, _ptr(f, torch.float64), _ptr(p, torch.float64), B, float(tol),
-                                  int(max_cycles), hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n_hist,
-                                  ctypes.byref(stats))
+        lib = _lib.load()
+        entry = lib.mg_solve_static if static_scratch else lib.mg_solve
+        rc = entry(self._ctx, _ptr(f, torch.float64), _ptr(p, torch.float64), B, float(tol), int(max_cycles),
+                   hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n_hist, ctypes.byref(stats))
         if rc < 0 and (raise_on_fail or rc not in (MG_ENOCONV, MG_EBREAKDOWN)):
-            raise MGError(rc, "mg_solve")
+            raise MGError(rc, "mg_solve_static" if static_scratch else "mg_solve")
         rows = hist.reshape(B, max_cycles + 1)
         hists = [rows[b, :n_hist[b]].tolist() for b in range(B)]
         out = stats.as_dict()
