@@ -60,7 +60,7 @@ constexpr double kBreakdownGrowth = 1e3;
 constexpr double kZeroRhs = 64.0 * 2.220446049250313e-16;
 
 // device scalar slots
-enum { S_FMEAN = 0, S_FNORM2 = 1, S_RNORM2 = 2, S_PMEAN = 3, S_DW = 4, S_DR = 5, S_ZW = 6, S_COUNT = 8 };
+enum { S_FMEAN = 0, S_FNORM2 = 1, S_RNORM2 = 2, S_PMEAN = 3, S_DW = 4, S_DR = 5, S_ZW = 6, S_ALPHA = 7, S_COUNT = 8 };
 
 struct Level {
   int n = 0, q = 0;
@@ -91,7 +91,7 @@ struct mg_ctx {
   double* partials = nullptr;
   double* scal = nullptr;
   long long* counters = nullptr;
-  double *kr = nullptr, *kz = nullptr, *kd = nullptr, *kw = nullptr;   // flexible-CG vectors
+  double *kr = nullptr, *kz = nullptr, *kd = nullptr, *kd2 = nullptr, *kw = nullptr;   // flexible-CG vectors
   double* host = nullptr;   // pinned, S_COUNT doubles
   hipEvent_t read_done = nullptr;   // the last read-back of scalars has landed in host
   long long active = 0, dropped = 0;
@@ -332,8 +332,14 @@ int solve_one(mg_ctx* c, const double* f, double* p, double tol, int max_cycles,
   ++nh;
   int status = MG_OK;
   if (c->flags & MG_KRYLOV) {
-    // flexible CG: r, z, d, w in the workspace; z = V(r) in FP64, or V32 on float(r)
-    double *kr = c->kr, *kz = c->kz, *kd = c->kd, *kw = c->kw;
+    // flexible CG: r, z, two directions and w in the workspace; z = V(r) in FP64, or V32
+    // on float(r).  One step: r -= alpha w (alpha = d.r / d.w); the convergence check;
+    // z = V(r); z.w; then one pass forms the new direction d' = z + beta d (beta =
+    // -z.w / d.w) in the other direction buffer, w = A d', d'.w and d'.r, and the update
+    // p += alpha d deferred from the step before (the last one is applied on exit).
+    double *kr = c->kr, *kz = c->kz, *kw = c->kw;
+    double* dirs[2] = {c->kd, c->kd2};
+    int cur = 0;   // dirs[cur] holds the current direction
     const int q = a.q;
     const float* z32 = mixed ? e32 : nullptr;
     const double* z64 = mixed ? nullptr : kz;
@@ -345,25 +351,38 @@ int solve_one(mg_ctx* c, const double* f, double* p, double tol, int max_cycles,
       if (mixed) return first_sweep<float>(c, e32, r32, nullptr, true);
       return first_sweep<double>(c, kz, kr, nullptr, true);
     };
+    // the new direction from z and the current one, with w = A d' and the two sums into
+    // partial sets 0 and 1; first: d' = z, no update of p
+    auto direction = [&](bool first) -> int {
+      const double* s_zw = first ? nullptr : c->scal + S_ZW;
+      const double* s_dw = first ? nullptr : c->scal + S_DW;
+      double* dnew = dirs[1 - cur];
+      int nb = 0;
+      if (mg::march_supported(q)) {
+        MG_HIP(mg::launch_fcg_x_march(z64, z32, dirs[cur], dnew, p, s_zw, s_dw, c->scal + S_ALPHA, kr, a.bx, a.by,
+                                      a.bz, a.rt, q, a.h, kw, part(c, 0), part(c, 1), &nb, c->stream));
+      } else {
+        MG_HIP(mg::launch_fcg_dir(z64, z32, dirs[cur], dnew, first ? nullptr : p, s_zw, s_dw, c->scal + S_ALPHA, q,
+                                  c->stream));
+        MG_HIP(mg::launch_fcg_aw(dnew, kr, a.bx, a.by, a.bz, a.rt, q, a.h, kw, part(c, 0), part(c, 1), &nb,
+                                 c->stream));
+      }
+      cur = 1 - cur;
+      MG_TRY(reduce_set(c, 0, nb, S_DW));
+      MG_TRY(reduce_set(c, 1, nb, S_DR));
+      return MG_OK;
+    };
     double* kz_zero = (mixed || zin) ? nullptr : kz;
     if (std::isfinite(r) && r > tol && max_cycles > 0) {
       // the first residual pass also wrote r (and zeroed the preconditioner output)
       MG_TRY(residual_norm(c, p, f, fshift, r32, e32_zero, kr, kz_zero));
       MG_TRY(precondition(false));
-      MG_HIP(mg::launch_fcg_dir(z64, z32, kd, nullptr, nullptr, q, c->stream));
+      MG_TRY(direction(true));
     }
     while (std::isfinite(r) && r > tol && *cycles < max_cycles) {
       int nb = 0;
-      if (mg::march_supported(q))
-        MG_HIP(mg::launch_fcg_aw_march(kd, kr, a.bx, a.by, a.bz, a.rt, q, a.h, kw, part(c, 0), part(c, 1), &nb,
-                                       c->stream));
-      else
-        MG_HIP(mg::launch_fcg_aw(kd, kr, a.bx, a.by, a.bz, a.rt, q, a.h, kw, part(c, 0), part(c, 1), &nb,
-                                 c->stream));
-      MG_TRY(reduce_set(c, 0, nb, S_DW));
-      MG_TRY(reduce_set(c, 1, nb, S_DR));
-      MG_HIP(mg::launch_fcg_update(p, kr, kd, kw, c->scal + S_DR, c->scal + S_DW, q, kz_zero,
-                                   mixed ? r32 : nullptr, mixed ? e32_zero : nullptr, part(c, 2), &nb, c->stream));
+      MG_HIP(mg::launch_fcg_rupdate(kr, kw, c->scal + S_DR, c->scal + S_DW, c->scal + S_ALPHA, q, kz_zero,
+                                    mixed ? r32 : nullptr, mixed ? e32_zero : nullptr, part(c, 2), &nb, c->stream));
       MG_TRY(reduce_set(c, 2, nb, S_RNORM2));
       ++*cycles;
       double sn[8];
@@ -374,16 +393,19 @@ int solve_one(mg_ctx* c, const double* f, double* p, double tol, int max_cycles,
       r = std::sqrt(sn[S_RNORM2]) / nf;
       if (hist) hist[nh] = r;
       ++nh;
-      if (!std::isfinite(r) || !(sn[S_DW] < 0.0) || r > kBreakdownGrowth * std::fmax(r0, 1.0)) {
-        status = fail(MG_EBREAKDOWN, "flexible CG breakdown after %d steps (residual %g, d.Ad %g)", *cycles, r,
-                      sn[S_DW]);
+      const bool broke = !std::isfinite(r) || !(sn[S_DW] < 0.0) || r > kBreakdownGrowth * std::fmax(r0, 1.0);
+      if (broke || r <= tol || *cycles >= max_cycles) {
+        // p += alpha d of this step, which the next direction pass would have applied
+        MG_HIP(mg::launch_fcg_padd(p, dirs[cur], c->scal + S_ALPHA, q, c->stream));
+        if (broke)
+          status = fail(MG_EBREAKDOWN, "flexible CG breakdown after %d steps (residual %g, d.Ad %g)", *cycles, r,
+                        sn[S_DW]);
         break;
       }
-      if (r <= tol || *cycles >= max_cycles) break;
       MG_TRY(precondition(ahead));
       MG_HIP(mg::launch_fcg_zw(z64, z32, kw, q, part(c, 3), &nb, c->stream));
       MG_TRY(reduce_set(c, 3, nb, S_ZW));
-      MG_HIP(mg::launch_fcg_dir(z64, z32, kd, c->scal + S_ZW, c->scal + S_DW, q, c->stream));
+      MG_TRY(direction(false));
     }
   }
   // Mixed refinement on a density-form finest grid: the FP64 update p + e and the next
@@ -555,6 +577,7 @@ int setup_impl(mg_ctx** out, void* workspace, size_t ws_bytes, const double* bx,
   c->kr = at<double>(c->ws, plan.kr);
   c->kz = at<double>(c->ws, plan.kz);
   c->kd = at<double>(c->ws, plan.kd);
+  c->kd2 = at<double>(c->ws, plan.kd2);
   c->kw = at<double>(c->ws, plan.kw);
 
   auto cleanup = [&](int rc) {
@@ -686,6 +709,7 @@ int make_lane(mg_ctx* ctx, unsigned char* ws, const mg::Plan& lp, int device, mg
   c->kr = at<double>(ws, lp.kr);
   c->kz = at<double>(ws, lp.kz);
   c->kd = at<double>(ws, lp.kd);
+  c->kd2 = at<double>(ws, lp.kd2);
   c->kw = at<double>(ws, lp.kw);
   *out = c;
   if (hipHostMalloc(reinterpret_cast<void**>(&c->host), sizeof(double) * S_COUNT, hipHostMallocDefault) != hipSuccess) {
@@ -811,6 +835,7 @@ class ScratchSwap {
     kr_ = c->kr;
     kz_ = c->kz;
     kd_ = c->kd;
+    kd2_ = c->kd2;
     kw_ = c->kw;
     for (int l = 0; l < c->L; ++l) {
       Level& a = c->lv[l];
@@ -829,6 +854,7 @@ class ScratchSwap {
     c->kr = at<double>(base, lp.kr);
     c->kz = at<double>(base, lp.kz);
     c->kd = at<double>(base, lp.kd);
+    c->kd2 = at<double>(base, lp.kd2);
     c->kw = at<double>(base, lp.kw);
   }
   ~ScratchSwap() {
@@ -838,6 +864,7 @@ class ScratchSwap {
     c_->kr = kr_;
     c_->kz = kz_;
     c_->kd = kd_;
+    c_->kd2 = kd2_;
     c_->kw = kw_;
   }
   ScratchSwap(const ScratchSwap&) = delete;
@@ -846,7 +873,7 @@ class ScratchSwap {
  private:
   mg_ctx* c_;
   Level saved_[mg::kMaxLevels];
-  double *partials_, *scal_, *kr_, *kz_, *kd_, *kw_;
+  double *partials_, *scal_, *kr_, *kz_, *kd_, *kd2_, *kw_;
 };
 
 }  // namespace

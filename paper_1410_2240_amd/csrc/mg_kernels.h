@@ -143,6 +143,15 @@ hipError_t launch_residual_norm_update_march(const double* p, const float* e, do
 hipError_t launch_fcg_aw_march(const double* d, const double* r, const double* bx, const double* by, const double* bz,
                                const double* rt, int q, double h, double* w, double* part_dw, double* part_dr,
                                int* nblocks, hipStream_t s);
+// The flexible-CG direction and product in one pass (grids of 32^3 and up): dn = z +
+// beta d (beta = -*s_zw / *s_dw; with s_zw = s_dw = null the first direction dn = z,
+// and d is not used), w = A dn, partial sums of dn.w and dn.r, and p += *s_alpha d
+// (the previous step's update, skipped on the first step).  z is z64 or z32 (exactly
+// one non-null); dn must not be d.
+hipError_t launch_fcg_x_march(const double* z64, const float* z32, const double* d, double* dn, double* p,
+                              const double* s_zw, const double* s_dw, const double* s_alpha, const double* r,
+                              const double* bx, const double* by, const double* bz, const double* rt, int q, double h,
+                              double* w, double* part_dw, double* part_dr, int* nblocks, hipStream_t s);
 
 // ---- FP64 finest-grid passes ------------------------------------------------------
 // partials[blockIdx] = sum over active cells of r^2, r = (f - fshift) - A p; optional
@@ -152,18 +161,21 @@ hipError_t launch_residual_norm(const double* p, const double* f, const double* 
                                 const double* bz, const double* rt, int q, double h, const double* fshift,
                                 float* r32, float* e32_zero, double* r64, double* z64, double* partials,
                                 int* nblocks, hipStream_t s);
-// flexible CG: w = A d with partial d.w and d.r; the update p += alpha d, r -= alpha w
-// (alpha = dr/dw read on the device) with partial ||r||^2; partial z.w; d = z + beta d
+// flexible CG: w = A d with partial d.w and d.r; the residual update r -= alpha w
+// (alpha = dr/dw read on the device and stored to *s_alpha) with partial ||r||^2; the
+// update p += *s_alpha d; partial z.w; dn = z + beta d (with p += *s_alpha d when p is
+// given; beta and the update skipped when s_zw is null, dn = z; dn may be d)
 hipError_t launch_fcg_aw(const double* d, const double* r, const double* bx, const double* by, const double* bz,
                          const double* rt, int q, double h, double* w, double* part_dw, double* part_dr, int* nblocks,
                          hipStream_t s);
-hipError_t launch_fcg_update(double* p, double* r, const double* d, const double* w, const double* s_dr,
-                             const double* s_dw, int q, double* z_zero, float* r32, float* e32_zero, double* part_rr,
-                             int* nblocks, hipStream_t s);
+hipError_t launch_fcg_rupdate(double* r, const double* w, const double* s_dr, const double* s_dw, double* s_alpha,
+                              int q, double* z_zero, float* r32, float* e32_zero, double* part_rr, int* nblocks,
+                              hipStream_t s);
+hipError_t launch_fcg_padd(double* p, const double* d, const double* s_alpha, int q, hipStream_t s);
 hipError_t launch_fcg_zw(const double* z64, const float* z32, const double* w, int q, double* part, int* nblocks,
                          hipStream_t s);
-hipError_t launch_fcg_dir(const double* z64, const float* z32, double* d, const double* s_zw, const double* s_dw,
-                          int q, hipStream_t s);
+hipError_t launch_fcg_dir(const double* z64, const float* z32, const double* d, double* dn, double* p,
+                          const double* s_zw, const double* s_dw, const double* s_alpha, int q, hipStream_t s);
 // mode 0: partials = sum_active x ; mode 1: sum_active (x - *shift)^2
 hipError_t launch_masked_sum(const double* x, const uint8_t* mask, int q, int mode, const double* shift,
                              double* partials, int* nblocks, hipStream_t s);

@@ -902,24 +902,23 @@ __global__ __launch_bounds__(kBlock) void k_fcg_aw(const double* __restrict__ d,
   }
 }
 
-// alpha = dr / dw;  p += alpha d;  r -= alpha w;  partial ||r||^2.  Leaves the next
-// preconditioner input ready: FP64 z = 0, or FP32 r32 = r and e32 = 0.
-__global__ __launch_bounds__(kBlock) void k_fcg_update(double* __restrict__ p, double* __restrict__ r,
-                                                       const double* __restrict__ d, const double* __restrict__ w,
-                                                       const double* __restrict__ s_dr,
-                                                       const double* __restrict__ s_dw, int total,
-                                                       double* __restrict__ z_zero, float* __restrict__ r32,
-                                                       float* __restrict__ e32_zero, double* __restrict__ part_rr) {
+// alpha = dr / dw (kept in *s_alpha for the deferred update of p);  r -= alpha w;
+// partial ||r||^2.  Leaves the next preconditioner input ready: FP64 z = 0, or FP32
+// r32 = r and e32 = 0.
+__global__ __launch_bounds__(kBlock) void k_fcg_rupdate(double* __restrict__ r, const double* __restrict__ w,
+                                                        const double* __restrict__ s_dr,
+                                                        const double* __restrict__ s_dw,
+                                                        double* __restrict__ s_alpha, int total,
+                                                        double* __restrict__ z_zero, float* __restrict__ r32,
+                                                        float* __restrict__ e32_zero, double* __restrict__ part_rr) {
   const double alpha = *s_dr / *s_dw;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *s_alpha = alpha;
   double rr = 0.0;
   for (int c = 2 * (blockIdx.x * kBlock + threadIdx.x); c < total; c += 2 * gridDim.x * kBlock) {
-    double2 pv = ld2(p, c), rv = ld2(r, c);
-    const double2 dv = ld2(d, c), wv = ld2(w, c);
-    pv.x += alpha * dv.x;
-    pv.y += alpha * dv.y;
+    double2 rv = ld2(r, c);
+    const double2 wv = ld2(w, c);
     rv.x -= alpha * wv.x;
     rv.y -= alpha * wv.y;
-    *reinterpret_cast<double2*>(p + c) = pv;
     *reinterpret_cast<double2*>(r + c) = rv;
     rr += rv.x * rv.x + rv.y * rv.y;
     if (r32) *reinterpret_cast<float2*>(r32 + c) = float2{static_cast<float>(rv.x), static_cast<float>(rv.y)};
@@ -928,6 +927,16 @@ __global__ __launch_bounds__(kBlock) void k_fcg_update(double* __restrict__ p, d
   }
   const double s = block_sum(rr);
   if (threadIdx.x == 0) part_rr[blockIdx.x] = s;
+}
+
+// p += alpha d (the last step's update of the solution)
+__global__ __launch_bounds__(kBlock) void k_fcg_padd(double* __restrict__ p, const double* __restrict__ d,
+                                                     const double* __restrict__ s_alpha, int total) {
+  const double alpha = *s_alpha;
+  const long long c = 2 * (static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x);
+  if (c >= total) return;
+  const double2 pv = ld2(p, static_cast<int>(c)), dv = ld2(d, static_cast<int>(c));
+  *reinterpret_cast<double2*>(p + c) = double2{fmad(alpha, dv.x, pv.x), fmad(alpha, dv.y, pv.y)};
 }
 
 // partial sums of z.w, z in FP64 (z64) or FP32 (z32)
@@ -952,8 +961,9 @@ __global__ __launch_bounds__(kBlock) void k_fcg_zw(const double* __restrict__ z6
 
 // d = z + beta d with beta = -zw / dw (beta = 0 when s_zw is null: the first direction)
 __global__ __launch_bounds__(kBlock) void k_fcg_dir(const double* __restrict__ z64, const float* __restrict__ z32,
-                                                    double* __restrict__ d, const double* __restrict__ s_zw,
-                                                    const double* __restrict__ s_dw, int total) {
+                                                    const double* d, double* dn, double* p,
+                                                    const double* __restrict__ s_zw, const double* __restrict__ s_dw,
+                                                    const double* __restrict__ s_alpha, int total) {
   const double beta = s_zw ? -*s_zw / *s_dw : 0.0;
   const long long c = 2 * (static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x);
   if (c >= total) return;
@@ -964,8 +974,17 @@ __global__ __launch_bounds__(kBlock) void k_fcg_dir(const double* __restrict__ z
     const float2 zf = *reinterpret_cast<const float2*>(z32 + c);
     zv = double2{static_cast<double>(zf.x), static_cast<double>(zf.y)};
   }
-  const double2 dv = ld2(d, static_cast<int>(c));
-  *reinterpret_cast<double2*>(d + c) = double2{zv.x + beta * dv.x, zv.y + beta * dv.y};
+  if (!s_zw) {   // the first direction (d is not read)
+    *reinterpret_cast<double2*>(dn + c) = zv;
+    return;
+  }
+  const double2 dv = *reinterpret_cast<const double2*>(d + c);
+  if (p) {
+    const double alpha = *s_alpha;
+    const double2 pv = *reinterpret_cast<const double2*>(p + c);
+    *reinterpret_cast<double2*>(p + c) = double2{fmad(alpha, dv.x, pv.x), fmad(alpha, dv.y, pv.y)};
+  }
+  *reinterpret_cast<double2*>(dn + c) = double2{fmad(beta, dv.x, zv.x), fmad(beta, dv.y, zv.y)};
 }
 
 // ------------------------------------------- Runge-Kutta stage around the solve (FP64)
@@ -1182,13 +1201,18 @@ hipError_t launch_fcg_aw(const double* d, const double* r, const double* bx, con
   return hipGetLastError();
 }
 
-hipError_t launch_fcg_update(double* p, double* r, const double* d, const double* w, const double* s_dr,
-                             const double* s_dw, int q, double* z_zero, float* r32, float* e32_zero, double* part_rr,
-                             int* nblocks, hipStream_t s) {
+hipError_t launch_fcg_rupdate(double* r, const double* w, const double* s_dr, const double* s_dw, double* s_alpha,
+                              int q, double* z_zero, float* r32, float* e32_zero, double* part_rr, int* nblocks,
+                              hipStream_t s) {
   const int nb = reduction_blocks(1LL << (3 * q - 1));
-  hipLaunchKernelGGL(k_fcg_update, dim3(nb), dim3(kBlock), 0, s, p, r, d, w, s_dr, s_dw, 1 << (3 * q), z_zero, r32,
+  hipLaunchKernelGGL(k_fcg_rupdate, dim3(nb), dim3(kBlock), 0, s, r, w, s_dr, s_dw, s_alpha, 1 << (3 * q), z_zero, r32,
                      e32_zero, part_rr);
   *nblocks = nb;
+  return hipGetLastError();
+}
+
+hipError_t launch_fcg_padd(double* p, const double* d, const double* s_alpha, int q, hipStream_t s) {
+  hipLaunchKernelGGL(k_fcg_padd, dim3(grid_for(1LL << (3 * q - 1))), dim3(kBlock), 0, s, p, d, s_alpha, 1 << (3 * q));
   return hipGetLastError();
 }
 
@@ -1200,10 +1224,10 @@ hipError_t launch_fcg_zw(const double* z64, const float* z32, const double* w, i
   return hipGetLastError();
 }
 
-hipError_t launch_fcg_dir(const double* z64, const float* z32, double* d, const double* s_zw, const double* s_dw,
-                          int q, hipStream_t s) {
-  hipLaunchKernelGGL(k_fcg_dir, dim3(grid_for(1LL << (3 * q - 1))), dim3(kBlock), 0, s, z64, z32, d, s_zw, s_dw,
-                     1 << (3 * q));
+hipError_t launch_fcg_dir(const double* z64, const float* z32, const double* d, double* dn, double* p,
+                          const double* s_zw, const double* s_dw, const double* s_alpha, int q, hipStream_t s) {
+  hipLaunchKernelGGL(k_fcg_dir, dim3(grid_for(1LL << (3 * q - 1))), dim3(kBlock), 0, s, z64, z32, d, dn, p, s_zw, s_dw,
+                     s_alpha, 1 << (3 * q));
   return hipGetLastError();
 }
 

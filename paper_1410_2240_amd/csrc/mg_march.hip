@@ -13,6 +13,11 @@
 //   RESTRICT  fc = mean of r over the 8 children of each coarse cell (the pair's two
 //             cells on two rows and two planes), ec = 0
 //   AW        w = A d (flexible CG) with partial sums of d.w and d.r
+//   FCGX      the flexible-CG direction and product in one pass: d = z + beta d_old
+//             (z in FP64 or FP32; d = z on the first step), w = A d, partial sums of
+//             d.w and d.r, and the previous step's p += alpha d_old, deferred to this
+//             pass (d_old, z are read at every point of the stencil; d goes to a
+//             second buffer, since neighbouring threads still read d_old)
 // Coefficients come from the face arrays, or (RHO) from the density form rt: each
 // face is face_beta(rt_L, rt_R), formed once per plane and thread (the faces to the
 // plane below are carried from the previous plane).  Sums are explicit fused
@@ -34,7 +39,7 @@ using buf::Rsrc;
 using buf::Vec2;
 
 constexpr int kMarchThreads = 256;
-enum { kModeNorm = 0, kModeRestrict = 1, kModeAw = 2, kModeNormUpdate = 3 };
+enum { kModeNorm = 0, kModeRestrict = 1, kModeAw = 2, kModeNormUpdate = 3, kModeFcgX = 4 };
 
 __device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
@@ -68,6 +73,15 @@ struct MarchArgs {
   // p + e written to pout
   const float* eu;
   double* pout;
+  // FCGX (p = d_old): z (one of the two), beta = -s_zw / s_dw (none on the first step:
+  // d = z), the new direction dn, and p += s_alpha d_old on pp (none on the first step)
+  const double* zx64;
+  const float* zx32;
+  const double* s_zw;
+  const double* s_dw;
+  const double* s_alpha;
+  double* dn;
+  double* pp;
 };
 
 // The six faces of the two cells of an x-pair
@@ -124,6 +138,8 @@ __global__ __launch_bounds__(kMarchThreads) void k_residual_march(MarchArgs<T> a
   static_assert(sizeof(T) == 8 || MODE == kModeRestrict, "FP32 marches restrict only");
   constexpr bool UPD = MODE == kModeNormUpdate;
   constexpr bool NORM = MODE == kModeNorm || UPD;
+  constexpr bool FX = MODE == kModeFcgX;
+  constexpr bool PROD = MODE == kModeAw || FX;   // w = A d and the two dot products
   static_assert(!UPD || RHO, "the update mode reads activity from the density form");
   constexpr int PAIRS = TX / 2;                 // x-pairs per tile row
   constexpr int RP = kMarchThreads / PAIRS;     // row pairs per tile
@@ -144,12 +160,37 @@ __global__ __launch_bounds__(kMarchThreads) void k_residual_march(MarchArgs<T> a
   const unsigned od = off_of<T>(ip, ja - 1, q), ou = off_of<T>(ip, jb + 1, q);
   const unsigned ola = off_of<T>(ip - 1, ja, q), ora = off_of<T>(ip + 2, ja, q);
   const unsigned olb = off_of<T>(ip - 1, jb, q), orb = off_of<T>(ip + 2, jb, q);
-  const T fs = (MODE != kModeAw && a.fshift) ? static_cast<T>(*a.fshift) : zero;
+  const T fs = (!PROD && a.fshift) ? static_cast<T>(*a.fshift) : zero;
+  // FCGX: the new direction from z and d_old at one point of the stencil
+  const bool fx_first = FX && a.s_zw == nullptr;
+  const double fx_beta = (FX && !fx_first) ? -*a.s_zw / *a.s_dw : 0.0;
+  auto zload2 = [&](int kk, unsigned off) -> double2 {
+    if (a.zx64) return ld2(plane_rsrc(a.zx64, kk, q), off, 0.0);
+    const float2 zf = ld2(plane_rsrc(a.zx32, kk, q), off >> 1, 0.0f);
+    return double2{static_cast<double>(zf.x), static_cast<double>(zf.y)};
+  };
+  auto zload1 = [&](int kk, unsigned off) -> double {
+    if (a.zx64) return ld1(plane_rsrc(a.zx64, kk, q), off, 0.0);
+    return static_cast<double>(ld1(plane_rsrc(a.zx32, kk, q), off >> 1, 0.0f));
+  };
+  auto dn2 = [&](double2 d, double2 z) -> double2 {
+    return fx_first ? z : double2{__builtin_fma(fx_beta, d.x, z.x), __builtin_fma(fx_beta, d.y, z.y)};
+  };
+  auto dn1 = [&](double d, double z) -> double { return fx_first ? z : __builtin_fma(fx_beta, d, z); };
 
   // window: the pair's p on the planes below, at and above the current one (rows a, b)
   const Rsrc p_lo = plane_rsrc(a.p, k0 - 1, q), p_c = plane_rsrc(a.p, k0, q);
   V2 pa_lo = ld2(p_lo, oa, zero), pb_lo = ld2(p_lo, ob, zero);
   V2 pa = ld2(p_c, oa, zero), pb = ld2(p_c, ob, zero);
+  V2 dca{zero, zero}, dcb{zero, zero};   // FCGX: d_old of the pair on the current plane
+  if constexpr (FX) {
+    dca = pa;
+    dcb = pb;
+    pa_lo = dn2(pa_lo, zload2(k0 - 1, oa));
+    pb_lo = dn2(pb_lo, zload2(k0 - 1, ob));
+    pa = dn2(pa, zload2(k0, oa));
+    pb = dn2(pb, zload2(k0, ob));
+  }
   // faces to the plane below (carried), and for the density form the pair's density
   V2 za, zb;                 // zm of rows a, b on the current plane
   V2 ra, rb;                 // density form: rt of the pair on the current plane
@@ -180,6 +221,19 @@ __global__ __launch_bounds__(kMarchThreads) void k_residual_march(MarchArgs<T> a
     V2 pd = ld2(pk, od, zero), pup = ld2(pk, ou, zero);
     T pla = ld1(pk, ola, zero), pra = ld1(pk, ora, zero);
     T plb = ld1(pk, olb, zero), prb = ld1(pk, orb, zero);
+    V2 dha{zero, zero}, dhb{zero, zero};   // FCGX: d_old of the pair on the plane above
+    if constexpr (FX) {
+      dha = pa_hi;
+      dhb = pb_hi;
+      pa_hi = dn2(pa_hi, zload2(k + 1, oa));
+      pb_hi = dn2(pb_hi, zload2(k + 1, ob));
+      pd = dn2(pd, zload2(k, od));
+      pup = dn2(pup, zload2(k, ou));
+      pla = dn1(pla, zload1(k, ola));
+      pra = dn1(pra, zload1(k, ora));
+      plb = dn1(plb, zload1(k, olb));
+      prb = dn1(prb, zload1(k, orb));
+    }
     float2 ea_hi, eb_hi, ed, eup;   // UPD: the correction at the same places
     float ela, era, elb, erb;
     if constexpr (UPD) {
@@ -194,7 +248,7 @@ __global__ __launch_bounds__(kMarchThreads) void k_residual_march(MarchArgs<T> a
       erb = ld1(ek, orb >> 1, 0.0f);
     }
     V2 fa{zero, zero}, fb{zero, zero};
-    if constexpr (MODE != kModeAw) {
+    if constexpr (!PROD) {
       const Rsrc fk = plane_rsrc(a.f, k, q);
       fa = ld2(fk, oa, zero);
       fb = ld2(fk, ob, zero);
@@ -300,6 +354,19 @@ __global__ __launch_bounds__(kMarchThreads) void k_residual_march(MarchArgs<T> a
       const double2 wa{-r0a, -r1a}, wb{-r0b, -r1b};
       stream_store(a.w + ca, wa);   // read again only by the update pass
       stream_store(a.w + cb, wb);
+      if constexpr (FX) {
+        // the new direction (read again after the next cycle), and the previous step's
+        // update of p with the old direction
+        stream_store(a.dn + ca, pa);
+        stream_store(a.dn + cb, pb);
+        if (a.pp) {
+          const double alpha = *a.s_alpha;
+          const double2 xa = *reinterpret_cast<const double2*>(a.pp + ca);
+          const double2 xb = *reinterpret_cast<const double2*>(a.pp + cb);
+          stream_store(a.pp + ca, double2{__builtin_fma(alpha, dca.x, xa.x), __builtin_fma(alpha, dca.y, xa.y)});
+          stream_store(a.pp + cb, double2{__builtin_fma(alpha, dcb.x, xb.x), __builtin_fma(alpha, dcb.y, xb.y)});
+        }
+      }
       const double2 rva = ld2(plane_rsrc(a.r, k, q), oa, 0.0), rvb = ld2(plane_rsrc(a.r, k, q), ob, 0.0);
       acc = fmad(pa.y, wa.y, fmad(pa.x, wa.x, acc));
       acc = fmad(pb.y, wb.y, fmad(pb.x, wb.x, acc));
@@ -312,11 +379,15 @@ __global__ __launch_bounds__(kMarchThreads) void k_residual_march(MarchArgs<T> a
     pb = pb_hi;
     za = za_next;
     zb = zb_next;
+    if constexpr (FX) {
+      dca = dha;
+      dcb = dhb;
+    }
   }
   if constexpr (NORM) {
     const double s = block_sum(acc);
     if (tid == 0) a.partials[bid] = s;
-  } else if constexpr (MODE == kModeAw) {
+  } else if constexpr (PROD) {
     const double s1 = block_sum(acc);
     __syncthreads();
     const double s2 = block_sum(acc2);
@@ -443,6 +514,34 @@ hipError_t launch_fcg_aw_march(const double* d, const double* r, const double* b
   a.partials = part_dw;
   a.partials2 = part_dr;
   return launch_form<kModeAw>(a, nblocks, s);
+}
+
+hipError_t launch_fcg_x_march(const double* z64, const float* z32, const double* d, double* dn, double* p,
+                              const double* s_zw, const double* s_dw, const double* s_alpha, const double* r,
+                              const double* bx, const double* by, const double* bz, const double* rt, int q, double h,
+                              double* w, double* part_dw, double* part_dr, int* nblocks, hipStream_t s) {
+  if ((z64 == nullptr) == (z32 == nullptr) || !d || !dn || dn == d || (s_zw == nullptr) != (s_dw == nullptr))
+    return hipErrorInvalidValue;
+  MarchArgs<double> a{};
+  a.p = d;
+  a.bx = bx;
+  a.by = by;
+  a.bz = bz;
+  a.rt = rt;
+  a.q = q;
+  a.inv_h2 = 1.0 / (h * h);
+  a.r = r;
+  a.w = w;
+  a.partials = part_dw;
+  a.partials2 = part_dr;
+  a.zx64 = z64;
+  a.zx32 = z32;
+  a.s_zw = s_zw;
+  a.s_dw = s_dw;
+  a.s_alpha = s_alpha;
+  a.dn = dn;
+  a.pp = s_zw ? p : nullptr;
+  return launch_form<kModeFcgX>(a, nblocks, s);
 }
 
 }  // namespace mg

@@ -74,6 +74,7 @@ int build_plan(int n, int flags, Plan* plan) {
     p.kr = c.take(fine);
     p.kz = c.take(fine);
     p.kd = c.take(fine);
+    p.kd2 = c.take(fine);
     p.kw = c.take(fine);
   }
   const size_t nc = static_cast<size_t>(kCoarsest) * kCoarsest * kCoarsest;
@@ -118,6 +119,7 @@ int build_lane_plan(int n, int flags, Plan* plan) {
     p.kr = c.take(fine);
     p.kz = c.take(fine);
     p.kd = c.take(fine);
+    p.kd2 = c.take(fine);
     p.kw = c.take(fine);
   }
   p.pinv = kAbsent;

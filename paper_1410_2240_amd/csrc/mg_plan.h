@@ -42,8 +42,9 @@ struct Plan {
   int levels = 0;
   int flags = 0;
   LevelPlan lv[kMaxLevels];
-  // finest-grid FP64 vectors of the flexible-CG outer iteration (Krylov flag only)
-  size_t kr = kAbsent, kz = kAbsent, kd = kAbsent, kw = kAbsent;
+  // finest-grid FP64 vectors of the flexible-CG outer iteration (Krylov flag only):
+  // residual, preconditioned residual, two directions (old and new), and A d
+  size_t kr = kAbsent, kz = kAbsent, kd = kAbsent, kd2 = kAbsent, kw = kAbsent;
   size_t pinv = 0;       // (4^3)^2 doubles: pseudo-inverse of the coarsest operator
   size_t partials = 0;   // kPartialSets x kNumPartials doubles
   size_t scalars = 0;    // 32 doubles of device scalars

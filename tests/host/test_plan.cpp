@@ -60,7 +60,7 @@ static void check_layout(int n, int flags) {
   }
   const size_t fine = static_cast<size_t>(n) * n * n * 8;
   if (flags & 2) {
-    for (size_t o : {p.kr, p.kz, p.kd, p.kw}) spans.push_back({o, fine});
+    for (size_t o : {p.kr, p.kz, p.kd, p.kd2, p.kw}) spans.push_back({o, fine});
   } else {
     CHECK(p.kr == mg::kAbsent && p.kw == mg::kAbsent);
   }
@@ -107,7 +107,7 @@ static void check_lane_layout(int n, int flags) {
   }
   const size_t fine = static_cast<size_t>(n) * n * n * 8;
   if (flags & 2) {
-    for (size_t o : {p.kr, p.kz, p.kd, p.kw}) spans.push_back({o, fine});
+    for (size_t o : {p.kr, p.kz, p.kd, p.kd2, p.kw}) spans.push_back({o, fine});
   } else {
     CHECK(p.kr == mg::kAbsent && p.kw == mg::kAbsent);
   }

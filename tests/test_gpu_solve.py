@@ -502,3 +502,36 @@ def test_runge_kutta_stage_leaves_no_divergence_256():
     mg.project(U, p, R, dt)
     d = mg.divergence(U, None, 1.0)
     assert float(d.abs().max()) <= 1e-9 * float(f.abs().max()) * dt * 10
+
+
+@pytest.mark.parametrize("N,mixed", [(16, False), (64, False), (64, True)])
+def test_fcg_on_a_workspace_of_nan_patterns(N, mixed):
+    """The first flexible-CG direction is z itself: no buffer is read before the solve
+    writes it.  A workspace filled with 0xFF bytes (NaN bit patterns in every double)
+    before mg_setup_from_rho gives the same bits as one filled with zeros.  Called
+    through the C ABI with workspaces the test fills (16^3 runs the grid-stride
+    passes, 64^3 the z-marching ones)."""
+    import ctypes
+    from paper_1410_2240_amd import _lib
+    lib = _lib.load()
+    inp, _ = workload("c2", N)
+    rho, mask, f = dev(inp.rho), dev(inp.mask), dev(inp.f)
+    flags = _lib.MG_KRYLOV | (_lib.MG_MIXED if mixed else 0)
+    size = lib.mg_workspace_size(_lib.dims3(N), flags)
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    out = []
+    for fill in (0, 0xFF):
+        ws = torch.full((size,), fill, dtype=torch.uint8, device="cuda")
+        ctx = ctypes.c_void_p()
+        assert lib.mg_setup_from_rho(ctypes.byref(ctx), ctypes.c_void_p(ws.data_ptr()), size,
+                                     ctypes.c_void_p(rho.data_ptr()), ctypes.c_void_p(mask.data_ptr()),
+                                     _lib.dims3(N), 1.0 / N, flags, stream) == 0
+        p = torch.zeros_like(f)
+        hist = np.zeros(101)
+        nh = (ctypes.c_int * 1)()
+        rc = lib.mg_solve(ctx, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(p.data_ptr()), 1, 1e-10, 100,
+                          hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), nh, None)
+        lib.mg_destroy(ctx)
+        assert rc == 0, (fill, rc, _lib.last_error())
+        out.append((host(p), hist[:nh[0]].copy()))
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
