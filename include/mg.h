@@ -207,7 +207,14 @@ int mg_add_lanes(mg_ctx* ctx, void* workspace, size_t ws_bytes, int lanes);
 int mg_solve_static(mg_ctx* ctx, const double* f, double* p, int batch, double tol, int max_cycles,
                     double* hist, int* n_hist, mg_stats* stats);
 
-/* Ap_b = A p_b on the finest grid (0 in the body). */
+/*
+ * Ap_b = A p_b on the finest grid: the discrete operator of eq. (pois) in the
+ * finite-volume form of eq. (integral2), (A p)_c = h^-2 sum over the faces of c of
+ * beta_f (p_neighbour - p_c), with the context's face products (section 3.1); 0 on
+ * inactive cells.  p and Ap are DEVICE [batch][N][N][N] arrays owned by the caller;
+ * Ap is overwritten.  Stream-ordered, no synchronisation.  MG_EINVAL for a null
+ * context or pointer or batch < 1.
+ */
 int mg_apply(mg_ctx* ctx, const double* p, double* Ap, int batch);
 
 /*
