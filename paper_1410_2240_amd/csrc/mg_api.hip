@@ -137,6 +137,23 @@ long long cells(const Level& a) { return static_cast<long long>(a.n) * a.n * a.n
 // be zero, so the first one-pass sweep does not read it (p's memory may then hold
 // anything; half-sweep grids still need it zeroed).  first_done: the first sweep
 // (p -> second buffer) has already been queued (see first_sweep), so start from its output.
+// Grids whose sweeps run two to a pass: FP32 density form (the finest grid of a mixed
+// context's FP32 cycles), 256^3 and up.
+template <typename T>
+bool two_sweep_grid(const mg_ctx* c, int l) {
+  return std::is_same<T, float>::value && c->view<T>(l).rt != nullptr && mg::fused2_supported(c->lv[l].q);
+}
+
+template <typename T>
+hipError_t launch_two_sweeps(const mg_ctx* c, int l, const T* pin, T* pout, const T* f, const double* fshift, int order,
+                             bool zero_in) {
+  if constexpr (std::is_same<T, float>::value) {
+    const Level& a = c->lv[l];
+    return mg::launch_rbgs_fused2(pin, pout, f, c->view<T>(l).rt, a.q, a.h, order, fshift, zero_in ? 1 : 0, c->stream);
+  }
+  return hipErrorInvalidValue;
+}
+
 template <typename T>
 int smooth(mg_ctx* c, int l, T* p, const T* f, const double* fshift, int sweeps, int order, bool zero_in = false,
            bool first_done = false) {
@@ -145,7 +162,17 @@ int smooth(mg_ctx* c, int l, T* p, const T* f, const double* fshift, int sweeps,
   if (mg::fused_sweep_supported(a.q)) {
     T* src = first_done ? v.t : p;
     T* dst = first_done ? p : v.t;
-    for (int s = first_done ? 1 : 0; s < sweeps; ++s) {
+    const bool two = two_sweep_grid<T>(c, l);
+    int s = first_done ? (two ? 2 : 1) : 0;   // first_sweep queued one pass
+    if (two) {   // pairs of sweeps in one pass each
+      for (; s + 2 <= sweeps; s += 2) {
+        MG_HIP(launch_two_sweeps<T>(c, l, src, dst, f, fshift, order, zero_in && s == 0));
+        T* tmp = src;
+        src = dst;
+        dst = tmp;
+      }
+    }
+    for (; s < sweeps; ++s) {
       MG_HIP(mg::launch_rbgs_fused<T>(src, dst, f, v.bx, v.by, v.bz, v.rt, a.q, a.h, order, fshift,
                                       zero_in && s == 0, c->stream));
       T* tmp = src;
@@ -180,10 +207,15 @@ int residual_restrict(mg_ctx* c, int l, const T* p, const T* f, const double* fs
 // writes only the grid's second buffer (p is read, or not at all with zero_in), so it can
 // be queued before the host has read the convergence check, and the cycle then starts
 // from its output (vcycle with first_done); if the check ends the solve, it is discarded.
+// On a grid that sweeps two to a pass the whole pre-smoothing (both sweeps) is queued.
 template <typename T>
 int first_sweep(mg_ctx* c, T* p, const T* f, const double* fshift, bool zero_in) {
   const Level& a = c->lv[0];
   const View<T> v = c->view<T>(0);
+  if (two_sweep_grid<T>(c, 0)) {
+    MG_HIP(launch_two_sweeps<T>(c, 0, p, v.t, f, fshift, MG_PRE, zero_in));
+    return MG_OK;
+  }
   MG_HIP(mg::launch_rbgs_fused<T>(p, v.t, f, v.bx, v.by, v.bz, v.rt, a.q, a.h, MG_PRE, fshift, zero_in, c->stream));
   return MG_OK;
 }
@@ -214,6 +246,17 @@ int vcycle(mg_ctx* c, int l, T* p, const T* f, const double* fshift, bool zero_i
     return MG_OK;
   }
   const View<T> next = c->view<T>(l + 1);
+  if (two_sweep_grid<T>(c, l)) {
+    // pre-smoothing p -> t in one pass (or already queued by first_sweep), restriction and
+    // prolongation on t, post-smoothing t -> p in one pass: no copies
+    T* t = c->view<T>(l).t;
+    if (!first_done) MG_HIP(launch_two_sweeps<T>(c, l, p, t, f, fshift, MG_PRE, zero_in));
+    MG_TRY(residual_restrict<T>(c, l, t, f, fshift, next.f, next.e));
+    MG_TRY(vcycle<T>(c, l + 1, next.e, next.f, nullptr, true));
+    MG_HIP(mg::launch_prolong_add<T>(next.e, t, c->lv[l].mask, c->lv[l].q, c->stream));
+    MG_HIP(launch_two_sweeps<T>(c, l, t, p, f, fshift, MG_POST, false));
+    return MG_OK;
+  }
   MG_TRY(smooth<T>(c, l, p, f, fshift, 2, MG_PRE, zero_in, first_done));
   MG_TRY(residual_restrict<T>(c, l, p, f, fshift, next.f, next.e));
   MG_TRY(vcycle<T>(c, l + 1, next.e, next.f, nullptr, true));   // restriction zeroed next.e

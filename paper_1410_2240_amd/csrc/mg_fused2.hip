@@ -1,0 +1,285 @@
+// Two red-black Gauss-Seidel sweeps in a single pass over memory (CDNA4, FP32 density
+// form: the finest grid of the FP32 cycles of a mixed-precision solve).
+//
+// A V(2,2) cycle smooths twice in a row before the restriction and twice after the
+// prolongation.  The one-pass sweep (mg_fused.hip) reads p, f and the density once per
+// sweep; this kernel does both sweeps of a pair in one march up z, so they are read once
+// for the two.  Call the four half-sweeps A1, B1, A2, B2 (A the colour that goes first).
+// At step k a workgroup does A1 on plane k+3, B1 on plane k+2, A2 on plane k+1 and B2 on
+// plane k, and writes plane k out.  Each half-sweep needs the one before it on the planes
+// either side (B1 on k+2 reads A1 on k+1..k+3, A2 on k+1 reads B1 on k..k+2, B2 on k reads
+// A2 on k-1..k+1), and each reads the other colour on its own plane as the step before
+// left it, so this order gives exactly the four half-sweeps one after another.
+//
+// Tiles of 128 x 16 cells.  Neighbouring workgroups update the same halo cells, so every
+// half-sweep is also computed on a ring around the tile, from values the workgroup has
+// itself: A1 on a ring 3 cells wide, B1 on 2, A2 on 1, B2 on the tile.  Planes of p and
+// of the density (rho on active cells, +inf elsewhere and beyond the z walls) are staged
+// in LDS with a 4-cell halo (136 x 24 cells), six planes at a time: k..k+4 are read in
+// step k, and the sixth slot takes plane k+5 while a slower wave is still in step k.  No
+// thread reads plane k-1 from LDS in step k: the one value B2 needs from it (the cell
+// below, and its density) the thread computed itself two steps earlier and keeps.
+//
+// Work is given out by column: a thread owns one x-pair of the tile (a wave per tile
+// row) and up to one x-pair of the ring, and at step k does all four updates in the one
+// column of each pair whose cell on plane k+3 has colour A (the colours alternate with z,
+// so the four planes' cells in that column are A, B, A, B).  Everything one update needs
+// from the planes below and above is then in its own column: only the in-plane
+// neighbours come from other threads, and those were written in an earlier step, before
+// its barrier.  One barrier per step.
+//
+// A z-chunk [k0, k0 + kc) is entered six steps early: A1 from plane k0-3, B1 from k0-2,
+// A2 from k0-1, B2 from k0 (all within the grid), recomputing what the chunk below
+// computes on those planes from the same inputs, so chunks need no communication.
+// The arithmetic of every update (the faces face_beta(rt_L, rt_R), their sum, the fused
+// multiply-adds in a fixed order and the division) is that of the one-pass sweep, so two
+// sweeps of either kernel give the same bits.
+#include <type_traits>
+
+#include "mg_buffer.h"
+#include "mg_kernels.h"
+
+namespace mg {
+
+namespace {
+
+using buf::ld2;
+using buf::off_of;
+using buf::plane_rsrc;
+using buf::Rsrc;
+
+constexpr int kTX = 128, kTY = 16;          // tile
+constexpr int kNT = kTX / 2 * kTY;          // 1024 threads, one per tile x-pair
+constexpr int kH = kTY + 8, kW = kTX + 8;   // staged box: ring 4
+constexpr int kWP = kW / 2;                 // x-pairs per box row (68)
+constexpr int kSlots = 6;
+constexpr int kBoxPairs = kH * kWP;         // 1632
+constexpr int kPer = (kBoxPairs + kNT - 1) / kNT;   // staged pairs per thread (2)
+// ring pairs: box rows 1..3 and 20..22 whole (6 x 68), rows 4..19 at pairs 0, 1, 66, 67
+constexpr int kRingPairs = 6 * kWP + kTY * 4;       // 472
+static_assert(kRingPairs <= kNT, "one ring pair per thread at most");
+
+__device__ __forceinline__ int slot(int kk) { return (kk + 2 * kSlots) % kSlots; }   // kk >= -kSlots
+
+// ring distance of box cell (r, c): 0 on the tile, up to 4 on the box edge
+__device__ __forceinline__ int ring_of(int r, int c) {
+  const int dy = max(max(4 - r, r - (kTY + 3)), 0);
+  const int dx = max(max(4 - c, c - (kTX + 3)), 0);
+  return max(dx, dy);
+}
+
+template <bool ZIN>
+__global__ __launch_bounds__(kNT) void k_rbgs_fused2(const float* __restrict__ pin, float* __restrict__ pout,
+                                                     const float* __restrict__ f, const float* __restrict__ rt, int q,
+                                                     int kc, float h2, int first, const double* __restrict__ fshift) {
+  __shared__ float P[kSlots][kH][2][kWP];
+  __shared__ float R[kSlots][kH][2][kWP];
+  const int n = 1 << q;
+  const int tid = threadIdx.x;
+  const int G = gridDim.x, bid = blockIdx.x;
+  const int lid = (G % 8 == 0) ? (bid % 8) * (G / 8) + bid / 8 : bid;   // neighbours on one XCD
+  const int ntx = n / kTX, nty = n / kTY;
+  const int i0 = (lid % ntx) * kTX;
+  const int j0 = ((lid / ntx) % nty) * kTY;
+  const int k0 = (lid / (ntx * nty)) * kc;
+  const int k1 = k0 + kc;
+  const float fs = fshift ? static_cast<float>(*fshift) : 0.0f;
+  const float inf = __builtin_huge_valf();
+
+  // ---- staging: box pair e = tid + u * kNT of each plane, global -> registers -> LDS
+  unsigned so[kPer];
+  int sr[kPer], sc[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int e = tid + u * kNT;
+    sr[u] = e < kBoxPairs ? e / kWP : -1;
+    sc[u] = e % kWP;
+    so[u] = e < kBoxPairs ? off_of<float>(i0 - 4 + 2 * sc[u], j0 - 4 + sr[u], q) : 0u;
+  }
+  float2 pn[kPer], rn[kPer];
+  auto fetch = [&](int kk) {   // a plane outside the grid reads 0
+    const Rsrc pk = plane_rsrc(pin, kk, q), rk = plane_rsrc(rt, kk, q);
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      pn[u] = ZIN ? float2{0.0f, 0.0f} : ld2(pk, so[u], 0.0f);
+      rn[u] = ld2(rk, so[u], 0.0f);
+    }
+  };
+  auto store = [&](int kk) {   // densities beyond a z wall are +inf, replaced here (not at the load)
+    const int s = slot(kk);
+    const bool in = kk >= 0 && kk < n;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      if (sr[u] >= 0) {
+        P[s][sr[u]][0][sc[u]] = pn[u].x;
+        P[s][sr[u]][1][sc[u]] = pn[u].y;
+        R[s][sr[u]][0][sc[u]] = in ? rn[u].x : inf;
+        R[s][sr[u]][1][sc[u]] = in ? rn[u].y : inf;
+      }
+    }
+  };
+
+  // ---- the pairs this thread owns: one of the tile (wave = tile row), one of the ring
+  const int tr = tid / (kTX / 2) + 4;              // box row of the tile pair
+  const int tcp = tid % (kTX / 2) + 2;             // box pair index (columns 2 tcp, 2 tcp + 1)
+  const int tj = j0 + tr - 4;                      // its global row (no wrap: inside the tile)
+  const unsigned tf_off = off_of<float>(i0 + 2 * (tcp - 2), tj, q);
+  const bool has_ring = tid < kRingPairs;
+  int gr = 0, gcp = 0;
+  if (tid < 6 * kWP) {
+    const int row = tid / kWP;
+    gr = row < 3 ? 1 + row : kTY + 1 + row;        // rows 1, 2, 3, 20, 21, 22
+    gcp = tid % kWP;
+  } else {
+    const int e = tid - 6 * kWP;
+    gr = 4 + e / 4;
+    const int w = e % 4;
+    gcp = w < 2 ? w : kWP - 4 + w;                 // pairs 0, 1, 66, 67
+  }
+  const int gj = j0 - 4 + gr;
+  const unsigned gf_off = has_ring ? off_of<float>(i0 - 4 + 2 * gcp, gj, q) : 0u;
+
+  // f of the owned pairs on planes k .. k+3 (index 0..3), and the load of plane k+4
+  float2 tfw[4], gfw[4], tfn, gfn;
+  auto load_f = [&](int kk, float2& t, float2& g) {
+    const Rsrc fk = plane_rsrc(f, kk, q);
+    t = ld2(fk, tf_off, 0.0f);
+    g = has_ring ? ld2(fk, gf_off, 0.0f) : float2{0.0f, 0.0f};
+  };
+
+  // The six faces of box cell (r, c) on plane kk (the density below comes in as lo_r,
+  // the one above from the next slot), and the Gauss-Seidel update of that cell from
+  // them.  The second sweep's update of a cell comes two steps after the first one's,
+  // in the same column, on the same faces: they are kept in registers for it.
+  struct Faces {
+    float xm, xp, ym, yp, zm, zp;
+  };
+  auto faces = [&](int kk, int r, int c, float lo_r) {
+    const int s = slot(kk), sa = slot(kk + 1);
+    const int cl = c - 1, cr = c + 1;
+    const float rc = R[s][r][c & 1][c >> 1];
+    return Faces{face_beta(R[s][r][cl & 1][cl >> 1], rc), face_beta(rc, R[s][r][cr & 1][cr >> 1]),
+                 face_beta(R[s][r - 1][c & 1][c >> 1], rc), face_beta(rc, R[s][r + 1][c & 1][c >> 1]),
+                 face_beta(lo_r, rc), face_beta(rc, R[sa][r][c & 1][c >> 1])};
+  };
+  auto gs = [&](int kk, int r, int c, const Faces& F, float lo_p, float fv) {
+    const int s = slot(kk), sa = slot(kk + 1);
+    const int cl = c - 1, cr = c + 1;
+    const float D = F.xm + F.xp + F.ym + F.yp + F.zm + F.zp;
+    if (D > 0.0f) {
+      const float S = __builtin_fmaf(F.zp, P[sa][r][c & 1][c >> 1], __builtin_fmaf(F.zm, lo_p,
+                      __builtin_fmaf(F.yp, P[s][r + 1][c & 1][c >> 1], __builtin_fmaf(F.ym, P[s][r - 1][c & 1][c >> 1],
+                      __builtin_fmaf(F.xp, P[s][r][cr & 1][cr >> 1], F.xm * P[s][r][cl & 1][cl >> 1])))));
+      P[s][r][c & 1][c >> 1] = __builtin_fmaf(-h2, fv - fs, S) / D;
+    }
+  };
+  auto lds_p = [&](int kk, int r, int c) { return P[slot(kk)][r][c & 1][c >> 1]; };
+  auto lds_r = [&](int kk, int r, int c) { return R[slot(kk)][r][c & 1][c >> 1]; };
+
+  // lower bounds of the four half-sweeps in this chunk
+  const int lo_a1 = max(k0 - 3, 0), lo_b1 = max(k0 - 2, 0), lo_a2 = max(k0 - 1, 0);
+  // per parity of the step: the tile column's cell on plane k-1 (value after A2, and its
+  // density) for B2 on plane k, and the faces of the A1 and B1 updates for A2 and B2 two
+  // steps on (tile), and of the ring's A1 for its A2
+  float below_p[2] = {0.0f, 0.0f}, below_r[2] = {inf, inf};
+  Faces ta[2], tb[2], ga[2];
+
+  // ---- prologue: planes k0-6 .. k0-3 staged, k0-2 in registers, f of k0-6 .. k0-3
+  const int ks = k0 - 6;   // even: chunks start at multiples of kc >= 8
+  for (int kk = ks; kk < ks + 4; ++kk) {
+    fetch(kk);
+    store(kk);
+  }
+  fetch(ks + 4);
+#pragma unroll
+  for (int d = 0; d < 4; ++d) load_f(ks + d, tfw[d], gfw[d]);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+
+  // one step; PAR = k & 1, known at compile time so the kept registers are named
+  auto step = [&](int k, auto par_tag) {
+    constexpr int PAR = decltype(par_tag)::value;
+    store(k + 4);
+    fetch(k + 5);
+    load_f(k + 4, tfn, gfn);
+    __syncthreads();
+    const int ka = k + 3, kb = k + 2, kA = k + 1;
+    // the tile pair: the column whose cell on plane k+3 has colour A (uniform per wave)
+    {
+      const int odd = (first + tj + k + 1) & 1;
+      const int c = 2 * tcp + odd;
+      const Faces a2f = ta[PAR], b2f = tb[PAR];   // from step k-2, before this step's A1, B1
+      if (ka >= lo_a1 && ka < n) {
+        ta[PAR] = faces(ka, tr, c, lds_r(kb, tr, c));
+        gs(ka, tr, c, ta[PAR], lds_p(kb, tr, c), odd ? tfw[3].y : tfw[3].x);
+      }
+      if (kb >= lo_b1 && kb < n) {
+        tb[PAR] = faces(kb, tr, c, lds_r(kA, tr, c));
+        gs(kb, tr, c, tb[PAR], lds_p(kA, tr, c), odd ? tfw[2].y : tfw[2].x);
+      }
+      if (kA >= lo_a2 && kA < n) gs(kA, tr, c, a2f, lds_p(k, tr, c), odd ? tfw[1].y : tfw[1].x);
+      if (k >= k0 && k < n) {
+        gs(k, tr, c, b2f, below_p[PAR], odd ? tfw[0].y : tfw[0].x);
+        // plane k is final in both columns of the pair (the other one since A2 at step k-1)
+        const float v0 = lds_p(k, tr, 2 * tcp), v1 = lds_p(k, tr, 2 * tcp + 1);
+        *reinterpret_cast<float2*>(reinterpret_cast<char*>(pout + (static_cast<long long>(k) << (2 * q))) + tf_off) =
+            float2{v0, v1};
+      }
+      // this column's cell on plane k+1 is used by B2 on plane k+2, two steps on
+      below_p[PAR] = lds_p(kA, tr, c);
+      below_r[PAR] = lds_r(kA, tr, c);
+    }
+    // the ring pair: as far as its ring distance allows (per lane)
+    if (has_ring) {
+      const int odd = (first + gj + k + 1) & 1;
+      const int c = 2 * gcp + odd;
+      const int d = ring_of(gr, c);
+      const Faces a2f = ga[PAR];
+      if (d <= 3 && ka >= lo_a1 && ka < n) {
+        ga[PAR] = faces(ka, gr, c, lds_r(kb, gr, c));
+        gs(ka, gr, c, ga[PAR], lds_p(kb, gr, c), odd ? gfw[3].y : gfw[3].x);
+      }
+      if (d <= 2 && kb >= lo_b1 && kb < n)
+        gs(kb, gr, c, faces(kb, gr, c, lds_r(kA, gr, c)), lds_p(kA, gr, c), odd ? gfw[2].y : gfw[2].x);
+      if (d <= 1 && kA >= lo_a2 && kA < n) gs(kA, gr, c, a2f, lds_p(k, gr, c), odd ? gfw[1].y : gfw[1].x);
+    }
+    tfw[0] = tfw[1];
+    tfw[1] = tfw[2];
+    tfw[2] = tfw[3];
+    tfw[3] = tfn;
+    gfw[0] = gfw[1];
+    gfw[1] = gfw[2];
+    gfw[2] = gfw[3];
+    gfw[3] = gfn;
+  };
+  // kc + 6 steps, an even number, starting on an even plane
+  for (int k = ks; k < k1; k += 2) {
+    step(k, std::integral_constant<int, 0>{});
+    step(k + 1, std::integral_constant<int, 1>{});
+  }
+}
+
+}  // namespace
+
+int fused2_supported(int q) { return (1 << q) >= 256; }
+
+hipError_t launch_rbgs_fused2(const float* pin, float* pout, const float* f, const float* rt, int q, double h, int order,
+                              const double* fshift, int zero_in, hipStream_t s) {
+  const int n = 1 << q;
+  if (n < 256 || !rt || pin == pout) return hipErrorInvalidValue;
+  const long long tiles = static_cast<long long>(n / kTX) * (n / kTY);
+  // z-chunks as long as possible while every compute unit still gets a workgroup
+  int kc = n;
+  while (kc > 8 && tiles * (n / kc) < 256) kc /= 2;
+  const long long blocks = tiles * (n / kc);
+  const float h2 = static_cast<float>(h * h);
+  const int first = order == 0 ? 0 : 1;   // pre-smoothing: red first; post-smoothing: black first
+  const dim3 grid(static_cast<unsigned>(blocks));
+  if (zero_in)
+    hipLaunchKernelGGL(k_rbgs_fused2<true>, grid, dim3(kNT), 0, s, pin, pout, f, rt, q, kc, h2, first, fshift);
+  else
+    hipLaunchKernelGGL(k_rbgs_fused2<false>, grid, dim3(kNT), 0, s, pin, pout, f, rt, q, kc, h2, first, fshift);
+  return hipGetLastError();
+}
+
+}  // namespace mg
