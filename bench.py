@@ -32,6 +32,9 @@ HBM_PEAK_GBS = 8000.0
 # the coarser grids.
 VCYCLE_SCALARS_F64 = 21.25 + 31.25 / 7
 VCYCLE_SCALARS_F32 = VCYCLE_SCALARS_F64
+# FP32 cycles on grids of 256^3 and up sweep two at a time on the finest grid (p, f and
+# the density read once, p written once per pair): 2 x 4 + 3.125 + 2.125 = 13.25
+VCYCLE_SCALARS_F32_TWO = 13.25 + 31.25 / 7
 # the same count with three face arrays on the finest grid too (31.25 x 8 / 7)
 VCYCLE_SCALARS_FACE = 31.25 * 8 / 7
 
@@ -201,6 +204,29 @@ def main():
     log(f"mixed projection ({outer}) {rmx['ms']:.2f} ms, {rmx['cycles']:.0f} steps, status {rmx['status']}, "
         f"relres {rmx['final_relres']:.3e}")
     vc32 = vcycle_ms(rmx["mg"], f, mask, torch.float32)
+    # the FP32 cycles' finest-grid smoother: two red-black sweeps per pass (grids of 256^3
+    # and up); four sweeps = two passes p -> t -> p, as in a cycle
+    two_sweep = None
+    if N >= 256:
+        f32 = ((f - f[mask.bool()].mean()) * mask).float()
+        p32 = torch.zeros_like(f32)
+        mgx = rmx["mg"]
+        mgx.smooth(0, p32, f32, 4, 0)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            mgx.smooth(0, p32, f32, 4, 0)
+        b.record()
+        torch.cuda.synchronize()
+        pass_ms = a.elapsed_time(b) / (2 * reps)
+        two_sweep = {"kernel": "rbgs_fused2 (finest grid of the FP32 cycles, density form, two red-black sweeps "
+                               "per launch)", "launch_ms": pass_ms, "bytes_per_launch": n * 4 * 4,
+                     "achieved_GBs": n * 4 * 4 / (pass_ms * 1e-3) / 1e9,
+                     "frac": n * 4 * 4 / (pass_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "note": "ALU-bound (face coefficients formed from the density at every update); "
+                             "two one-pass FP32 sweeps move twice the bytes"}
+        del f32, p32, mgx
     rmx.pop("mg"), rmx.pop("p")
     torch.cuda.empty_cache()
 
@@ -256,7 +282,8 @@ def main():
         # algorithmic scalars per finest cell per V(2,2) cycle of the design that runs
         # (density form on the finest grid), and against the face-array count
         "vcycle_roofline_frac": {"fp64": scalars_f64 * 8 * n / (vc64 * 1e-3) / (HBM_PEAK_GBS * 1e9),
-                                 "fp32": VCYCLE_SCALARS_F32 * 4 * n / (vc32 * 1e-3) / (HBM_PEAK_GBS * 1e9),
+                                 "fp32": (VCYCLE_SCALARS_F32_TWO if N >= 256 else VCYCLE_SCALARS_F32) * 4 * n
+                                 / (vc32 * 1e-3) / (HBM_PEAK_GBS * 1e9),
                                  "fp64_face_array_count": VCYCLE_SCALARS_FACE * 8 * n / (vc64 * 1e-3)
                                  / (HBM_PEAK_GBS * 1e9),
                                  "fp32_face_array_count": VCYCLE_SCALARS_FACE * 4 * n / (vc32 * 1e-3)
@@ -265,6 +292,7 @@ def main():
                      "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "launch_ms": launch_ms, "bytes_per_launch": sweep_bytes},
+        "fp32_two_sweep_pass": two_sweep,
         "input_gen_s": t_gen,
         **legs,
     }
