@@ -59,8 +59,6 @@ constexpr int kPer = (kBoxPairs + kNT - 1) / kNT;   // staged pairs per thread (
 constexpr int kRingPairs = 6 * kWP + kTY * 4;       // 472
 static_assert(kRingPairs <= kNT, "one ring pair per thread at most");
 
-__device__ __forceinline__ int slot(int kk) { return (kk + 2 * kSlots) % kSlots; }   // kk >= -kSlots
-
 // ring distance of box cell (r, c): 0 on the tile, up to 4 on the box edge
 __device__ __forceinline__ int ring_of(int r, int c) {
   const int dy = max(max(4 - r, r - (kTY + 3)), 0);
@@ -86,15 +84,25 @@ __global__ __launch_bounds__(kNT) void k_rbgs_fused2(const float* __restrict__ p
   const float fs = fshift ? static_cast<float>(*fshift) : 0.0f;
   const float inf = __builtin_huge_valf();
 
+  // ---- LDS addressing.  Box cell (r, c) of slot s is element ((s kH + r) 2 + (c & 1)) kWP
+  // + (c >> 1) of P and of R.  Slots go round with the plane's distance from the chunk's
+  // first step ks, and the march is unrolled by the six slots, so every slot is known at
+  // compile time: an access is an offset the thread computed once plus an immediate.
+  constexpr int kRow = 2 * kWP;      // floats per box row
+  constexpr int kSlot = kH * kRow;   // floats per slot
+  float* const Pf = &P[0][0][0][0];
+  float* const Rf = &R[0][0][0][0];
+  using std::integral_constant;
+
   // ---- staging: box pair e = tid + u * kNT of each plane, global -> registers -> LDS
   unsigned so[kPer];
-  int sr[kPer], sc[kPer];
+  int sl[kPer];   // LDS offset of the pair's even column in a slot (-1: none)
 #pragma unroll
   for (int u = 0; u < kPer; ++u) {
     const int e = tid + u * kNT;
-    sr[u] = e < kBoxPairs ? e / kWP : -1;
-    sc[u] = e % kWP;
-    so[u] = e < kBoxPairs ? off_of<float>(i0 - 4 + 2 * sc[u], j0 - 4 + sr[u], q) : 0u;
+    const int r = e / kWP, x = e % kWP;
+    sl[u] = e < kBoxPairs ? r * kRow + x : -1;
+    so[u] = e < kBoxPairs ? off_of<float>(i0 - 4 + 2 * x, j0 - 4 + r, q) : 0u;
   }
   float2 pn[kPer], rn[kPer];
   auto fetch = [&](int kk) {   // a plane outside the grid reads 0
@@ -105,25 +113,42 @@ __global__ __launch_bounds__(kNT) void k_rbgs_fused2(const float* __restrict__ p
       rn[u] = ld2(rk, so[u], 0.0f);
     }
   };
-  auto store = [&](int kk) {   // densities beyond a z wall are +inf, replaced here (not at the load)
-    const int s = slot(kk);
+  // plane kk into slot S; densities beyond a z wall are +inf, replaced here (not at the load)
+  auto store = [&](int kk, auto s_tag) {
+    constexpr int S = decltype(s_tag)::value * kSlot;
     const bool in = kk >= 0 && kk < n;
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
-      if (sr[u] >= 0) {
-        P[s][sr[u]][0][sc[u]] = pn[u].x;
-        P[s][sr[u]][1][sc[u]] = pn[u].y;
-        R[s][sr[u]][0][sc[u]] = in ? rn[u].x : inf;
-        R[s][sr[u]][1][sc[u]] = in ? rn[u].y : inf;
+      if (sl[u] >= 0) {
+        Pf[S + sl[u]] = pn[u].x;
+        Pf[S + sl[u] + kWP] = pn[u].y;
+        Rf[S + sl[u]] = in ? rn[u].x : inf;
+        Rf[S + sl[u] + kWP] = in ? rn[u].y : inf;
       }
     }
   };
 
-  // ---- the pairs this thread owns: one of the tile (wave = tile row), one of the ring
+  // A cell of the box in a slot: its own offset and that of its left neighbour (the
+  // right one is the next element after the left one in either column parity).
+  struct Cell {
+    int own, left;
+  };
+  // column c = 2 x + o of box row r
+  auto cell_of = [&](int r, int x, int o) {
+    return o ? Cell{r * kRow + kWP + x, r * kRow + x} : Cell{r * kRow + x, r * kRow + kWP + x - 1};
+  };
+
+  // ---- the pairs this thread owns: one of the tile (wave = tile row), one of the ring.
+  // Both work in the column of the pair whose cell on plane k+3 has colour A; with ks
+  // even that is column (first + j + 1 + (k - ks)) & 1 of the pair, so there are two
+  // cases, by the parity of k - ks.
   const int tr = tid / (kTX / 2) + 4;              // box row of the tile pair
   const int tcp = tid % (kTX / 2) + 2;             // box pair index (columns 2 tcp, 2 tcp + 1)
   const int tj = j0 + tr - 4;                      // its global row (no wrap: inside the tile)
   const unsigned tf_off = off_of<float>(i0 + 2 * (tcp - 2), tj, q);
+  const int out_off = tr * kRow + tcp;             // the pair's even column
+  const bool todd[2] = {((first + tj + 1) & 1) != 0, ((first + tj) & 1) != 0};
+  const Cell tcell[2] = {cell_of(tr, tcp, todd[0]), cell_of(tr, tcp, todd[1])};
   const bool has_ring = tid < kRingPairs;
   int gr = 0, gcp = 0;
   if (tid < 6 * kWP) {
@@ -138,124 +163,135 @@ __global__ __launch_bounds__(kNT) void k_rbgs_fused2(const float* __restrict__ p
   }
   const int gj = j0 - 4 + gr;
   const unsigned gf_off = has_ring ? off_of<float>(i0 - 4 + 2 * gcp, gj, q) : 0u;
+  const bool godd[2] = {((first + gj + 1) & 1) != 0, ((first + gj) & 1) != 0};
+  const Cell gcell[2] = {cell_of(gr, gcp, godd[0]), cell_of(gr, gcp, godd[1])};
+  const int gd[2] = {ring_of(gr, 2 * gcp + godd[0]), ring_of(gr, 2 * gcp + godd[1])};
 
-  // f of the owned pairs on planes k .. k+3 (index 0..3), and the load of plane k+4
-  float2 tfw[4], gfw[4], tfn, gfn;
+  // f of the owned pairs, plane kk at index (kk - ks) mod 6 (planes k .. k+3 in use at
+  // step k, k+4 arriving)
+  float2 tfw[kSlots], gfw[kSlots];
   auto load_f = [&](int kk, float2& t, float2& g) {
     const Rsrc fk = plane_rsrc(f, kk, q);
     t = ld2(fk, tf_off, 0.0f);
     g = has_ring ? ld2(fk, gf_off, 0.0f) : float2{0.0f, 0.0f};
   };
 
-  // The six faces of box cell (r, c) on plane kk (the density below comes in as lo_r,
-  // the one above from the next slot), and the Gauss-Seidel update of that cell from
-  // them.  The second sweep's update of a cell comes two steps after the first one's,
-  // in the same column, on the same faces: they are kept in registers for it.
+  // The six faces of a cell on the plane of slot S (the density below comes in as lo_r,
+  // the one above from slot SA), and the Gauss-Seidel update of that cell from them.
+  // The second sweep's update of a cell comes two steps after the first one's, in the
+  // same column, on the same faces: they are kept in registers for it.
   struct Faces {
     float xm, xp, ym, yp, zm, zp;
   };
-  auto faces = [&](int kk, int r, int c, float lo_r) {
-    const int s = slot(kk), sa = slot(kk + 1);
-    const int cl = c - 1, cr = c + 1;
-    const float rc = R[s][r][c & 1][c >> 1];
-    return Faces{face_beta(R[s][r][cl & 1][cl >> 1], rc), face_beta(rc, R[s][r][cr & 1][cr >> 1]),
-                 face_beta(R[s][r - 1][c & 1][c >> 1], rc), face_beta(rc, R[s][r + 1][c & 1][c >> 1]),
-                 face_beta(lo_r, rc), face_beta(rc, R[sa][r][c & 1][c >> 1])};
+  auto faces = [&](auto s_tag, auto sa_tag, const Cell& x, float lo_r) {
+    constexpr int S = decltype(s_tag)::value * kSlot, SA = decltype(sa_tag)::value * kSlot;
+    const float rc = Rf[S + x.own];
+    return Faces{face_beta(Rf[S + x.left], rc), face_beta(rc, Rf[S + x.left + 1]),
+                 face_beta(Rf[S + x.own - kRow], rc), face_beta(rc, Rf[S + x.own + kRow]),
+                 face_beta(lo_r, rc), face_beta(rc, Rf[SA + x.own])};
   };
-  auto gs = [&](int kk, int r, int c, const Faces& F, float lo_p, float fv) {
-    const int s = slot(kk), sa = slot(kk + 1);
-    const int cl = c - 1, cr = c + 1;
+  auto gs = [&](auto s_tag, auto sa_tag, const Cell& x, const Faces& F, float lo_p, float fv) {
+    constexpr int S = decltype(s_tag)::value * kSlot, SA = decltype(sa_tag)::value * kSlot;
     const float D = F.xm + F.xp + F.ym + F.yp + F.zm + F.zp;
     if (D > 0.0f) {
-      const float S = __builtin_fmaf(F.zp, P[sa][r][c & 1][c >> 1], __builtin_fmaf(F.zm, lo_p,
-                      __builtin_fmaf(F.yp, P[s][r + 1][c & 1][c >> 1], __builtin_fmaf(F.ym, P[s][r - 1][c & 1][c >> 1],
-                      __builtin_fmaf(F.xp, P[s][r][cr & 1][cr >> 1], F.xm * P[s][r][cl & 1][cl >> 1])))));
-      P[s][r][c & 1][c >> 1] = __builtin_fmaf(-h2, fv - fs, S) / D;
+      const float Sv = __builtin_fmaf(F.zp, Pf[SA + x.own], __builtin_fmaf(F.zm, lo_p,
+                       __builtin_fmaf(F.yp, Pf[S + x.own + kRow], __builtin_fmaf(F.ym, Pf[S + x.own - kRow],
+                       __builtin_fmaf(F.xp, Pf[S + x.left + 1], F.xm * Pf[S + x.left])))));
+      Pf[S + x.own] = __builtin_fmaf(-h2, fv - fs, Sv) / D;
     }
   };
-  auto lds_p = [&](int kk, int r, int c) { return P[slot(kk)][r][c & 1][c >> 1]; };
-  auto lds_r = [&](int kk, int r, int c) { return R[slot(kk)][r][c & 1][c >> 1]; };
 
   // lower bounds of the four half-sweeps in this chunk
   const int lo_a1 = max(k0 - 3, 0), lo_b1 = max(k0 - 2, 0), lo_a2 = max(k0 - 1, 0);
-  // per parity of the step: the tile column's cell on plane k-1 (value after A2, and its
-  // density) for B2 on plane k, and the faces of the A1 and B1 updates for A2 and B2 two
-  // steps on (tile), and of the ring's A1 for its A2
-  float below_p[2] = {0.0f, 0.0f}, below_r[2] = {inf, inf};
+  // per parity of the step: the tile column's cell on plane k-1 (value after A2) for B2
+  // on plane k, and the faces of the A1 and B1 updates for A2 and B2 two steps on
+  // (tile), and of the ring's A1 for its A2
+  float below_p[2] = {0.0f, 0.0f};
   Faces ta[2], tb[2], ga[2];
 
-  // ---- prologue: planes k0-6 .. k0-3 staged, k0-2 in registers, f of k0-6 .. k0-3
+  // ---- prologue: planes ks .. ks+3 staged (slots 0..3), ks+4 in registers, f of ks .. ks+3
   const int ks = k0 - 6;   // even: chunks start at multiples of kc >= 8
-  for (int kk = ks; kk < ks + 4; ++kk) {
-    fetch(kk);
-    store(kk);
-  }
+  fetch(ks);
+  store(ks, integral_constant<int, 0>{});
+  fetch(ks + 1);
+  store(ks + 1, integral_constant<int, 1>{});
+  fetch(ks + 2);
+  store(ks + 2, integral_constant<int, 2>{});
+  fetch(ks + 3);
+  store(ks + 3, integral_constant<int, 3>{});
   fetch(ks + 4);
 #pragma unroll
   for (int d = 0; d < 4; ++d) load_f(ks + d, tfw[d], gfw[d]);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
 
-  // one step; PAR = k & 1, known at compile time so the kept registers are named
-  auto step = [&](int k, auto par_tag) {
-    constexpr int PAR = decltype(par_tag)::value;
-    store(k + 4);
+  // one step; U = (k - ks) mod 6 at compile time, so slots and kept registers are named
+  auto step = [&](int k, auto u_tag) {
+    constexpr int U = decltype(u_tag)::value;
+    constexpr int PAR = U & 1;   // parity of k - ks
+    using S0 = integral_constant<int, U % kSlots>;   // slot (and f index) of plane k
+    using S1 = integral_constant<int, (U + 1) % kSlots>;
+    using S2 = integral_constant<int, (U + 2) % kSlots>;
+    using S3 = integral_constant<int, (U + 3) % kSlots>;
+    using S4 = integral_constant<int, (U + 4) % kSlots>;
+    store(k + 4, S4{});
     fetch(k + 5);
-    load_f(k + 4, tfn, gfn);
+    load_f(k + 4, tfw[S4::value], gfw[S4::value]);
     __syncthreads();
     const int ka = k + 3, kb = k + 2, kA = k + 1;
-    // the tile pair: the column whose cell on plane k+3 has colour A (uniform per wave)
     {
-      const int odd = (first + tj + k + 1) & 1;
-      const int c = 2 * tcp + odd;
+      const Cell c = tcell[PAR];
+      const bool odd = todd[PAR];
       const Faces a2f = ta[PAR], b2f = tb[PAR];   // from step k-2, before this step's A1, B1
       if (ka >= lo_a1 && ka < n) {
-        ta[PAR] = faces(ka, tr, c, lds_r(kb, tr, c));
-        gs(ka, tr, c, ta[PAR], lds_p(kb, tr, c), odd ? tfw[3].y : tfw[3].x);
+        ta[PAR] = faces(S3{}, S4{}, c, Rf[S2::value * kSlot + c.own]);
+        gs(S3{}, S4{}, c, ta[PAR], Pf[S2::value * kSlot + c.own], odd ? tfw[S3::value].y : tfw[S3::value].x);
       }
       if (kb >= lo_b1 && kb < n) {
-        tb[PAR] = faces(kb, tr, c, lds_r(kA, tr, c));
-        gs(kb, tr, c, tb[PAR], lds_p(kA, tr, c), odd ? tfw[2].y : tfw[2].x);
+        tb[PAR] = faces(S2{}, S3{}, c, Rf[S1::value * kSlot + c.own]);
+        gs(S2{}, S3{}, c, tb[PAR], Pf[S1::value * kSlot + c.own], odd ? tfw[S2::value].y : tfw[S2::value].x);
       }
-      if (kA >= lo_a2 && kA < n) gs(kA, tr, c, a2f, lds_p(k, tr, c), odd ? tfw[1].y : tfw[1].x);
+      if (kA >= lo_a2 && kA < n)
+        gs(S1{}, S2{}, c, a2f, Pf[S0::value * kSlot + c.own], odd ? tfw[S1::value].y : tfw[S1::value].x);
       if (k >= k0 && k < n) {
-        gs(k, tr, c, b2f, below_p[PAR], odd ? tfw[0].y : tfw[0].x);
+        gs(S0{}, S1{}, c, b2f, below_p[PAR], odd ? tfw[S0::value].y : tfw[S0::value].x);
         // plane k is final in both columns of the pair (the other one since A2 at step k-1)
-        const float v0 = lds_p(k, tr, 2 * tcp), v1 = lds_p(k, tr, 2 * tcp + 1);
+        const float v0 = Pf[S0::value * kSlot + out_off], v1 = Pf[S0::value * kSlot + out_off + kWP];
         *reinterpret_cast<float2*>(reinterpret_cast<char*>(pout + (static_cast<long long>(k) << (2 * q))) + tf_off) =
             float2{v0, v1};
       }
       // this column's cell on plane k+1 is used by B2 on plane k+2, two steps on
-      below_p[PAR] = lds_p(kA, tr, c);
-      below_r[PAR] = lds_r(kA, tr, c);
+      below_p[PAR] = Pf[S1::value * kSlot + c.own];
     }
     // the ring pair: as far as its ring distance allows (per lane)
     if (has_ring) {
-      const int odd = (first + gj + k + 1) & 1;
-      const int c = 2 * gcp + odd;
-      const int d = ring_of(gr, c);
+      const Cell c = gcell[PAR];
+      const bool odd = godd[PAR];
+      const int d = gd[PAR];
       const Faces a2f = ga[PAR];
       if (d <= 3 && ka >= lo_a1 && ka < n) {
-        ga[PAR] = faces(ka, gr, c, lds_r(kb, gr, c));
-        gs(ka, gr, c, ga[PAR], lds_p(kb, gr, c), odd ? gfw[3].y : gfw[3].x);
+        ga[PAR] = faces(S3{}, S4{}, c, Rf[S2::value * kSlot + c.own]);
+        gs(S3{}, S4{}, c, ga[PAR], Pf[S2::value * kSlot + c.own], odd ? gfw[S3::value].y : gfw[S3::value].x);
       }
       if (d <= 2 && kb >= lo_b1 && kb < n)
-        gs(kb, gr, c, faces(kb, gr, c, lds_r(kA, gr, c)), lds_p(kA, gr, c), odd ? gfw[2].y : gfw[2].x);
-      if (d <= 1 && kA >= lo_a2 && kA < n) gs(kA, gr, c, a2f, lds_p(k, gr, c), odd ? gfw[1].y : gfw[1].x);
+        gs(S2{}, S3{}, c, faces(S2{}, S3{}, c, Rf[S1::value * kSlot + c.own]), Pf[S1::value * kSlot + c.own],
+           odd ? gfw[S2::value].y : gfw[S2::value].x);
+      if (d <= 1 && kA >= lo_a2 && kA < n)
+        gs(S1{}, S2{}, c, a2f, Pf[S0::value * kSlot + c.own], odd ? gfw[S1::value].y : gfw[S1::value].x);
     }
-    tfw[0] = tfw[1];
-    tfw[1] = tfw[2];
-    tfw[2] = tfw[3];
-    tfw[3] = tfn;
-    gfw[0] = gfw[1];
-    gfw[1] = gfw[2];
-    gfw[2] = gfw[3];
-    gfw[3] = gfn;
   };
-  // kc + 6 steps, an even number, starting on an even plane
-  for (int k = ks; k < k1; k += 2) {
-    step(k, std::integral_constant<int, 0>{});
-    step(k + 1, std::integral_constant<int, 1>{});
+  // kc + 6 steps, an even number, from an even plane; six to a round of the slots
+  for (int k = ks; k < k1; k += kSlots) {
+    step(k, integral_constant<int, 0>{});
+    step(k + 1, integral_constant<int, 1>{});
+    if (k + 2 < k1) {
+      step(k + 2, integral_constant<int, 2>{});
+      step(k + 3, integral_constant<int, 3>{});
+    }
+    if (k + 4 < k1) {
+      step(k + 4, integral_constant<int, 4>{});
+      step(k + 5, integral_constant<int, 5>{});
+    }
   }
 }
 
