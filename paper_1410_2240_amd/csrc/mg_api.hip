@@ -137,21 +137,18 @@ long long cells(const Level& a) { return static_cast<long long>(a.n) * a.n * a.n
 // be zero, so the first one-pass sweep does not read it (p's memory may then hold
 // anything; half-sweep grids still need it zeroed).  first_done: the first sweep
 // (p -> second buffer) has already been queued (see first_sweep), so start from its output.
-// Grids whose sweeps run two to a pass: FP32 density form (the finest grid of a mixed
-// context's FP32 cycles), 256^3 and up.
+// Grids whose sweeps run two to a pass: the density form (the finest grid of a context
+// set up from rho, in its FP64 cycles and in a mixed context's FP32 cycles), 256^3 and up.
 template <typename T>
 bool two_sweep_grid(const mg_ctx* c, int l) {
-  return std::is_same<T, float>::value && c->view<T>(l).rt != nullptr && mg::fused2_supported(c->lv[l].q);
+  return c->view<T>(l).rt != nullptr && mg::fused2_supported(c->lv[l].q, sizeof(T) == 8);
 }
 
 template <typename T>
 hipError_t launch_two_sweeps(const mg_ctx* c, int l, const T* pin, T* pout, const T* f, const double* fshift, int order,
                              bool zero_in) {
-  if constexpr (std::is_same<T, float>::value) {
-    const Level& a = c->lv[l];
-    return mg::launch_rbgs_fused2(pin, pout, f, c->view<T>(l).rt, a.q, a.h, order, fshift, zero_in ? 1 : 0, c->stream);
-  }
-  return hipErrorInvalidValue;
+  const Level& a = c->lv[l];
+  return mg::launch_rbgs_fused2(pin, pout, f, c->view<T>(l).rt, a.q, a.h, order, fshift, zero_in ? 1 : 0, c->stream);
 }
 
 template <typename T>

@@ -1,5 +1,6 @@
-// Two red-black Gauss-Seidel sweeps in a single pass over memory (CDNA4, FP32 density
-// form: the finest grid of the FP32 cycles of a mixed-precision solve).
+// Two red-black Gauss-Seidel sweeps in a single pass over memory (CDNA4, density form:
+// the finest grid of a hierarchy built from rho, FP64 cycles and the FP32 cycles of a
+// mixed-precision solve).
 //
 // A V(2,2) cycle smooths twice in a row before the restriction and twice after the
 // prolongation.  The one-pass sweep (mg_fused.hip) reads p, f and the density once per
@@ -11,22 +12,22 @@
 // A2 on k-1..k+1), and each reads the other colour on its own plane as the step before
 // left it, so this order gives exactly the four half-sweeps one after another.
 //
-// Tiles of 128 x 16 cells.  Neighbouring workgroups update the same halo cells, so every
-// half-sweep is also computed on a ring around the tile, from values the workgroup has
-// itself: A1 on a ring 3 cells wide, B1 on 2, A2 on 1, B2 on the tile.  Planes of p and
-// of the density (rho on active cells, +inf elsewhere and beyond the z walls) are staged
-// in LDS with a 4-cell halo (136 x 24 cells), six planes at a time: k..k+4 are read in
-// step k, and the sixth slot takes plane k+5 while a slower wave is still in step k.  No
-// thread reads plane k-1 from LDS in step k: the one value B2 needs from it (the cell
-// below, and its density) the thread computed itself two steps earlier and keeps.
+// Tiles of 128 x 16 cells (FP32) or 32 x 32 (FP64).  Neighbouring workgroups update the
+// same halo cells, so every half-sweep is also computed on a ring around the tile, from
+// values the workgroup has itself: A1 on a ring 3 cells wide, B1 on 2, A2 on 1, B2 on the
+// tile.  Planes of p and of the density (rho on active cells, +inf elsewhere and beyond
+// the z walls) are staged in LDS with a 4-cell halo (136 x 24 or 40 x 40 cells), six
+// planes at a time: k..k+4 are read in step k, and the sixth slot takes plane k+5 while a
+// slower wave is still in step k.  No thread reads plane k-1 from LDS in step k: the one
+// value B2 needs from it (the cell below) the thread computed itself two steps earlier
+// and keeps.
 //
-// Work is given out by column: a thread owns one x-pair of the tile (a wave per tile
-// row) and up to one x-pair of the ring, and at step k does all four updates in the one
-// column of each pair whose cell on plane k+3 has colour A (the colours alternate with z,
-// so the four planes' cells in that column are A, B, A, B).  Everything one update needs
-// from the planes below and above is then in its own column: only the in-plane
-// neighbours come from other threads, and those were written in an earlier step, before
-// its barrier.  One barrier per step.
+// Work is given out by column: a thread owns one x-pair of the tile and up to one x-pair
+// of the ring, and at step k does all four updates in the one column of each pair whose
+// cell on plane k+3 has colour A (the colours alternate with z, so the four planes' cells
+// in that column are A, B, A, B).  Everything one update needs from the planes below and
+// above is then in its own column: only the in-plane neighbours come from other threads,
+// and those were written in an earlier step, before its barrier.  One barrier per step.
 //
 // A z-chunk [k0, k0 + kc) is entered six steps early: A1 from plane k0-3, B1 from k0-2,
 // A2 from k0-1, B2 from k0 (all within the grid), recomputing what the chunk below
@@ -48,30 +49,50 @@ using buf::off_of;
 using buf::plane_rsrc;
 using buf::Rsrc;
 
-constexpr int kTX = 128, kTY = 16;          // tile
-constexpr int kNT = kTX / 2 * kTY;          // 1024 threads, one per tile x-pair
-constexpr int kH = kTY + 8, kW = kTX + 8;   // staged box: ring 4
-constexpr int kWP = kW / 2;                 // x-pairs per box row (68)
+// Tile of a precision: FP32 128 x 16 (1024 threads, a wave per tile row); FP64 32 x 32
+// (512 threads, a wave per four tile rows), whose six staged planes of p and the density
+// with a 4-cell halo (40 x 40 cells, 154 KB) fit the 160 KB of LDS a workgroup has, with
+// the same ring cells per tile cell as the FP32 tile.
+template <typename T>
+struct Shape;
+template <>
+struct Shape<float> {
+  static constexpr int TX = 128, TY = 16;
+};
+template <>
+struct Shape<double> {
+  static constexpr int TX = 32, TY = 32;
+};
+
 constexpr int kSlots = 6;
-constexpr int kBoxPairs = kH * kWP;         // 1632
-constexpr int kPer = (kBoxPairs + kNT - 1) / kNT;   // staged pairs per thread (2)
-// ring pairs: box rows 1..3 and 20..22 whole (6 x 68), rows 4..19 at pairs 0, 1, 66, 67
-constexpr int kRingPairs = 6 * kWP + kTY * 4;       // 472
-static_assert(kRingPairs <= kNT, "one ring pair per thread at most");
 
 // ring distance of box cell (r, c): 0 on the tile, up to 4 on the box edge
+template <int TX, int TY>
 __device__ __forceinline__ int ring_of(int r, int c) {
-  const int dy = max(max(4 - r, r - (kTY + 3)), 0);
-  const int dx = max(max(4 - c, c - (kTX + 3)), 0);
+  const int dy = max(max(4 - r, r - (TY + 3)), 0);
+  const int dx = max(max(4 - c, c - (TX + 3)), 0);
   return max(dx, dy);
 }
 
-template <bool ZIN>
-__global__ __launch_bounds__(kNT) void k_rbgs_fused2(const float* __restrict__ pin, float* __restrict__ pout,
-                                                     const float* __restrict__ f, const float* __restrict__ rt, int q,
-                                                     int kc, float h2, int first, const double* __restrict__ fshift) {
-  __shared__ float P[kSlots][kH][2][kWP];
-  __shared__ float R[kSlots][kH][2][kWP];
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+template <typename T, bool ZIN>
+__global__ __launch_bounds__(Shape<T>::TX / 2 * Shape<T>::TY) void k_rbgs_fused2(
+    const T* __restrict__ pin, T* __restrict__ pout, const T* __restrict__ f, const T* __restrict__ rt, int q, int kc,
+    T h2, int first, const double* __restrict__ fshift) {
+  using V2 = typename buf::Vec2<T>::type;
+  constexpr int kTX = Shape<T>::TX, kTY = Shape<T>::TY;
+  constexpr int kNT = kTX / 2 * kTY;          // one thread per tile x-pair
+  constexpr int kH = kTY + 8, kW = kTX + 8;   // staged box: ring 4
+  constexpr int kWP = kW / 2;                 // x-pairs per box row
+  constexpr int kBoxPairs = kH * kWP;
+  constexpr int kPer = (kBoxPairs + kNT - 1) / kNT;   // staged pairs per thread
+  // ring pairs: box rows 1..3 and kTY+4..kTY+6 whole, the tile rows at pairs 0, 1, kWP-2, kWP-1
+  constexpr int kRingPairs = 6 * kWP + kTY * 4;
+  static_assert(kRingPairs <= kNT, "one ring pair per thread at most");
+  __shared__ T P[kSlots][kH][2][kWP];
+  __shared__ T R[kSlots][kH][2][kWP];
   const int n = 1 << q;
   const int tid = threadIdx.x;
   const int G = gridDim.x, bid = blockIdx.x;
@@ -81,8 +102,8 @@ __global__ __launch_bounds__(kNT) void k_rbgs_fused2(const float* __restrict__ p
   const int j0 = ((lid / ntx) % nty) * kTY;
   const int k0 = (lid / (ntx * nty)) * kc;
   const int k1 = k0 + kc;
-  const float fs = fshift ? static_cast<float>(*fshift) : 0.0f;
-  const float inf = __builtin_huge_valf();
+  const T fs = fshift ? static_cast<T>(*fshift) : T(0);
+  const T inf = __builtin_huge_val();
 
   // ---- LDS addressing.  Box cell (r, c) of slot s is element ((s kH + r) 2 + (c & 1)) kWP
   // + (c >> 1) of P and of R.  Slots go round with the plane's distance from the chunk's
@@ -90,8 +111,8 @@ __global__ __launch_bounds__(kNT) void k_rbgs_fused2(const float* __restrict__ p
   // compile time: an access is an offset the thread computed once plus an immediate.
   constexpr int kRow = 2 * kWP;      // floats per box row
   constexpr int kSlot = kH * kRow;   // floats per slot
-  float* const Pf = &P[0][0][0][0];
-  float* const Rf = &R[0][0][0][0];
+  T* const Pf = &P[0][0][0][0];
+  T* const Rf = &R[0][0][0][0];
   using std::integral_constant;
 
   // ---- staging: box pair e = tid + u * kNT of each plane, global -> registers -> LDS
@@ -102,15 +123,15 @@ __global__ __launch_bounds__(kNT) void k_rbgs_fused2(const float* __restrict__ p
     const int e = tid + u * kNT;
     const int r = e / kWP, x = e % kWP;
     sl[u] = e < kBoxPairs ? r * kRow + x : -1;
-    so[u] = e < kBoxPairs ? off_of<float>(i0 - 4 + 2 * x, j0 - 4 + r, q) : 0u;
+    so[u] = e < kBoxPairs ? off_of<T>(i0 - 4 + 2 * x, j0 - 4 + r, q) : 0u;
   }
-  float2 pn[kPer], rn[kPer];
+  V2 pn[kPer], rn[kPer];
   auto fetch = [&](int kk) {   // a plane outside the grid reads 0
     const Rsrc pk = plane_rsrc(pin, kk, q), rk = plane_rsrc(rt, kk, q);
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
-      pn[u] = ZIN ? float2{0.0f, 0.0f} : ld2(pk, so[u], 0.0f);
-      rn[u] = ld2(rk, so[u], 0.0f);
+      pn[u] = ZIN ? V2{T(0), T(0)} : ld2(pk, so[u], T(0));
+      rn[u] = ld2(rk, so[u], T(0));
     }
   };
   // plane kk into slot S; densities beyond a z wall are +inf, replaced here (not at the load)
@@ -145,7 +166,7 @@ __global__ __launch_bounds__(kNT) void k_rbgs_fused2(const float* __restrict__ p
   const int tr = tid / (kTX / 2) + 4;              // box row of the tile pair
   const int tcp = tid % (kTX / 2) + 2;             // box pair index (columns 2 tcp, 2 tcp + 1)
   const int tj = j0 + tr - 4;                      // its global row (no wrap: inside the tile)
-  const unsigned tf_off = off_of<float>(i0 + 2 * (tcp - 2), tj, q);
+  const unsigned tf_off = off_of<T>(i0 + 2 * (tcp - 2), tj, q);
   const int out_off = tr * kRow + tcp;             // the pair's even column
   const bool todd[2] = {((first + tj + 1) & 1) != 0, ((first + tj) & 1) != 0};
   const Cell tcell[2] = {cell_of(tr, tcp, todd[0]), cell_of(tr, tcp, todd[1])};
@@ -162,18 +183,18 @@ __global__ __launch_bounds__(kNT) void k_rbgs_fused2(const float* __restrict__ p
     gcp = w < 2 ? w : kWP - 4 + w;                 // pairs 0, 1, 66, 67
   }
   const int gj = j0 - 4 + gr;
-  const unsigned gf_off = has_ring ? off_of<float>(i0 - 4 + 2 * gcp, gj, q) : 0u;
+  const unsigned gf_off = has_ring ? off_of<T>(i0 - 4 + 2 * gcp, gj, q) : 0u;
   const bool godd[2] = {((first + gj + 1) & 1) != 0, ((first + gj) & 1) != 0};
   const Cell gcell[2] = {cell_of(gr, gcp, godd[0]), cell_of(gr, gcp, godd[1])};
-  const int gd[2] = {ring_of(gr, 2 * gcp + godd[0]), ring_of(gr, 2 * gcp + godd[1])};
+  const int gd[2] = {ring_of<kTX, kTY>(gr, 2 * gcp + godd[0]), ring_of<kTX, kTY>(gr, 2 * gcp + godd[1])};
 
   // f of the owned pairs, plane kk at index (kk - ks) mod 6 (planes k .. k+3 in use at
   // step k, k+4 arriving)
-  float2 tfw[kSlots], gfw[kSlots];
-  auto load_f = [&](int kk, float2& t, float2& g) {
+  V2 tfw[kSlots], gfw[kSlots];
+  auto load_f = [&](int kk, V2& t, V2& g) {
     const Rsrc fk = plane_rsrc(f, kk, q);
-    t = ld2(fk, tf_off, 0.0f);
-    g = has_ring ? ld2(fk, gf_off, 0.0f) : float2{0.0f, 0.0f};
+    t = ld2(fk, tf_off, T(0));
+    g = has_ring ? ld2(fk, gf_off, T(0)) : V2{T(0), T(0)};
   };
 
   // The six faces of a cell on the plane of slot S (the density below comes in as lo_r,
@@ -181,23 +202,22 @@ __global__ __launch_bounds__(kNT) void k_rbgs_fused2(const float* __restrict__ p
   // The second sweep's update of a cell comes two steps after the first one's, in the
   // same column, on the same faces: they are kept in registers for it.
   struct Faces {
-    float xm, xp, ym, yp, zm, zp;
+    T xm, xp, ym, yp, zm, zp;
   };
-  auto faces = [&](auto s_tag, auto sa_tag, const Cell& x, float lo_r) {
+  auto faces = [&](auto s_tag, auto sa_tag, const Cell& x, T lo_r) {
     constexpr int S = decltype(s_tag)::value * kSlot, SA = decltype(sa_tag)::value * kSlot;
-    const float rc = Rf[S + x.own];
+    const T rc = Rf[S + x.own];
     return Faces{face_beta(Rf[S + x.left], rc), face_beta(rc, Rf[S + x.left + 1]),
                  face_beta(Rf[S + x.own - kRow], rc), face_beta(rc, Rf[S + x.own + kRow]),
                  face_beta(lo_r, rc), face_beta(rc, Rf[SA + x.own])};
   };
-  auto gs = [&](auto s_tag, auto sa_tag, const Cell& x, const Faces& F, float lo_p, float fv) {
+  auto gs = [&](auto s_tag, auto sa_tag, const Cell& x, const Faces& F, T lo_p, T fv) {
     constexpr int S = decltype(s_tag)::value * kSlot, SA = decltype(sa_tag)::value * kSlot;
-    const float D = F.xm + F.xp + F.ym + F.yp + F.zm + F.zp;
-    if (D > 0.0f) {
-      const float Sv = __builtin_fmaf(F.zp, Pf[SA + x.own], __builtin_fmaf(F.zm, lo_p,
-                       __builtin_fmaf(F.yp, Pf[S + x.own + kRow], __builtin_fmaf(F.ym, Pf[S + x.own - kRow],
-                       __builtin_fmaf(F.xp, Pf[S + x.left + 1], F.xm * Pf[S + x.left])))));
-      Pf[S + x.own] = __builtin_fmaf(-h2, fv - fs, Sv) / D;
+    const T D = F.xm + F.xp + F.ym + F.yp + F.zm + F.zp;
+    if (D > T(0)) {
+      const T Sv = fma_t(F.zp, Pf[SA + x.own], fma_t(F.zm, lo_p, fma_t(F.yp, Pf[S + x.own + kRow],
+                   fma_t(F.ym, Pf[S + x.own - kRow], fma_t(F.xp, Pf[S + x.left + 1], F.xm * Pf[S + x.left])))));
+      Pf[S + x.own] = fma_t(-h2, fv - fs, Sv) / D;
     }
   };
 
@@ -206,7 +226,7 @@ __global__ __launch_bounds__(kNT) void k_rbgs_fused2(const float* __restrict__ p
   // per parity of the step: the tile column's cell on plane k-1 (value after A2) for B2
   // on plane k, and the faces of the A1 and B1 updates for A2 and B2 two steps on
   // (tile), and of the ring's A1 for its A2
-  float below_p[2] = {0.0f, 0.0f};
+  T below_p[2] = {T(0), T(0)};
   Faces ta[2], tb[2], ga[2];
 
   // ---- prologue: planes ks .. ks+3 staged (slots 0..3), ks+4 in registers, f of ks .. ks+3
@@ -256,9 +276,9 @@ __global__ __launch_bounds__(kNT) void k_rbgs_fused2(const float* __restrict__ p
       if (k >= k0 && k < n) {
         gs(S0{}, S1{}, c, b2f, below_p[PAR], odd ? tfw[S0::value].y : tfw[S0::value].x);
         // plane k is final in both columns of the pair (the other one since A2 at step k-1)
-        const float v0 = Pf[S0::value * kSlot + out_off], v1 = Pf[S0::value * kSlot + out_off + kWP];
-        *reinterpret_cast<float2*>(reinterpret_cast<char*>(pout + (static_cast<long long>(k) << (2 * q))) + tf_off) =
-            float2{v0, v1};
+        const T v0 = Pf[S0::value * kSlot + out_off], v1 = Pf[S0::value * kSlot + out_off + kWP];
+        *reinterpret_cast<V2*>(reinterpret_cast<char*>(pout + (static_cast<long long>(k) << (2 * q))) + tf_off) =
+            V2{v0, v1};
       }
       // this column's cell on plane k+1 is used by B2 on plane k+2, two steps on
       below_p[PAR] = Pf[S1::value * kSlot + c.own];
@@ -297,25 +317,32 @@ __global__ __launch_bounds__(kNT) void k_rbgs_fused2(const float* __restrict__ p
 
 }  // namespace
 
-int fused2_supported(int q) { return (1 << q) >= 256; }
+int fused2_supported(int q, int fp64) { return (1 << q) >= (fp64 ? 256 : 256); }
 
-hipError_t launch_rbgs_fused2(const float* pin, float* pout, const float* f, const float* rt, int q, double h, int order,
+template <typename T>
+hipError_t launch_rbgs_fused2(const T* pin, T* pout, const T* f, const T* rt, int q, double h, int order,
                               const double* fshift, int zero_in, hipStream_t s) {
+  constexpr int TX = Shape<T>::TX, TY = Shape<T>::TY;
   const int n = 1 << q;
-  if (n < 256 || !rt || pin == pout) return hipErrorInvalidValue;
-  const long long tiles = static_cast<long long>(n / kTX) * (n / kTY);
+  if (!fused2_supported(q, sizeof(T) == 8) || !rt || pin == pout) return hipErrorInvalidValue;
+  const long long tiles = static_cast<long long>(n / TX) * (n / TY);
   // z-chunks as long as possible while every compute unit still gets a workgroup
   int kc = n;
   while (kc > 8 && tiles * (n / kc) < 256) kc /= 2;
   const long long blocks = tiles * (n / kc);
-  const float h2 = static_cast<float>(h * h);
+  const T h2 = static_cast<T>(h * h);
   const int first = order == 0 ? 0 : 1;   // pre-smoothing: red first; post-smoothing: black first
-  const dim3 grid(static_cast<unsigned>(blocks));
+  const dim3 grid(static_cast<unsigned>(blocks)), block(TX / 2 * TY);
   if (zero_in)
-    hipLaunchKernelGGL(k_rbgs_fused2<true>, grid, dim3(kNT), 0, s, pin, pout, f, rt, q, kc, h2, first, fshift);
+    hipLaunchKernelGGL((k_rbgs_fused2<T, true>), grid, block, 0, s, pin, pout, f, rt, q, kc, h2, first, fshift);
   else
-    hipLaunchKernelGGL(k_rbgs_fused2<false>, grid, dim3(kNT), 0, s, pin, pout, f, rt, q, kc, h2, first, fshift);
+    hipLaunchKernelGGL((k_rbgs_fused2<T, false>), grid, block, 0, s, pin, pout, f, rt, q, kc, h2, first, fshift);
   return hipGetLastError();
 }
+
+template hipError_t launch_rbgs_fused2<float>(const float*, float*, const float*, const float*, int, double, int,
+                                              const double*, int, hipStream_t);
+template hipError_t launch_rbgs_fused2<double>(const double*, double*, const double*, const double*, int, double, int,
+                                               const double*, int, hipStream_t);
 
 }  // namespace mg

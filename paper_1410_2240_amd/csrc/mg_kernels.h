@@ -87,10 +87,11 @@ hipError_t launch_rbgs_half(T* p, const T* f, const T* bx, const T* by, const T*
 // rt != nullptr: coefficients from the density form instead of bx, by, bz.  zero_in:
 // the input is known to be zero (a correction's first sweep), so pin is not read.
 int fused_sweep_supported(int q);
-// Two red-black sweeps in one pass (FP32 density form, grids of 256^3 and up): pin ->
-// pout (distinct), order as launch_rbgs_fused; bit for bit two one-pass sweeps.
-int fused2_supported(int q);
-hipError_t launch_rbgs_fused2(const float* pin, float* pout, const float* f, const float* rt, int q, double h, int order,
+// Two red-black sweeps in one pass (density form, grids of 256^3 and up): pin -> pout
+// (distinct), order as launch_rbgs_fused; bit for bit two one-pass sweeps.
+int fused2_supported(int q, int fp64);
+template <typename T>
+hipError_t launch_rbgs_fused2(const T* pin, T* pout, const T* f, const T* rt, int q, double h, int order,
                               const double* fshift, int zero_in, hipStream_t s);
 template <typename T>
 hipError_t launch_rbgs_fused(const T* pin, T* pout, const T* f, const T* bx, const T* by, const T* bz, const T* rt,

@@ -1,5 +1,6 @@
-"""The FP32 two-sweep pass (two red-black sweeps per march up z, FP32 density form,
-grids of 256^3 and up) against the one-pass sweep and the oracle.
+"""The two-sweep pass (two red-black sweeps per march up z, density form, grids of 256^3
+and up; FP32 in 128 x 16 tiles, FP64 in 32 x 32 tiles) against the one-pass sweep and
+the oracle.
 
 Each update of the two-sweep pass does the arithmetic of the one-pass sweep on the same
 neighbour values, so two sweeps in one pass must equal two one-pass sweeps bit for bit:
@@ -28,11 +29,11 @@ def mixed_context(name, N):
     return inp, MG.from_rho(dev(inp.rho), dev(inp.mask), mixed=True)
 
 
-def random_fp32(inp, seed):
+def random_fp32(inp, seed, dtype=torch.float32):
     g = torch.Generator(device="cuda").manual_seed(seed)
     live = dev(inp.mask).bool()
-    p = torch.randn(inp.rho.shape, generator=g, device="cuda", dtype=torch.float32) * live
-    f = torch.randn(inp.rho.shape, generator=g, device="cuda", dtype=torch.float32) * live
+    p = torch.randn(inp.rho.shape, generator=g, device="cuda", dtype=dtype) * live
+    f = torch.randn(inp.rho.shape, generator=g, device="cuda", dtype=dtype) * live
     return p, f
 
 
@@ -42,25 +43,28 @@ def one_pass_sweeps(mg, p, f, sweeps, order):
     return p
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64], ids=["fp32", "fp64"])
 @pytest.mark.parametrize("name,N", [("c5", 256), ("c2", 256), pytest.param("c5", 512, marks=pytest.mark.slow)])
-def test_two_sweeps_equal_two_one_pass_sweeps(name, N):
+def test_two_sweeps_equal_two_one_pass_sweeps(name, N, dtype):
     inp, mg = mixed_context(name, N)
     for order in (0, 1):
         for sweeps in (2, 3, 4):
-            print(f"two-sweep pass {name} {N}^3 order={order} sweeps={sweeps}", flush=True)
-            p, f = random_fp32(inp, 10 * sweeps + order)
+            print(f"two-sweep pass {name} {N}^3 {dtype} order={order} sweeps={sweeps}", flush=True)
+            p, f = random_fp32(inp, 10 * sweeps + order, dtype)
             got = mg.smooth(0, p.clone(), f, sweeps, order)
             want = one_pass_sweeps(mg, p.clone(), f, sweeps, order)
             assert torch.equal(got, want), (order, sweeps)
 
 
 @pytest.mark.slow
-def test_two_sweeps_equal_two_one_pass_sweeps_1024():
-    """The headline grid: whole-column chunks, 512 workgroups in two rounds."""
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64], ids=["fp32", "fp64"])
+def test_two_sweeps_equal_two_one_pass_sweeps_1024(dtype):
+    """The headline grid: whole-column chunks (FP32: 512 workgroups in two rounds; FP64:
+    1024 in four)."""
     inp, mg = mixed_context("c5", 1024)
     for order in (0, 1):
-        print(f"two-sweep pass c5 1024^3 order={order}", flush=True)
-        p, f = random_fp32(inp, 1024 + order)
+        print(f"two-sweep pass c5 1024^3 {dtype} order={order}", flush=True)
+        p, f = random_fp32(inp, 1024 + order, dtype)
         got = mg.smooth(0, p.clone(), f, 2, order)
         want = one_pass_sweeps(mg, p.clone(), f, 2, order)
         assert torch.equal(got, want), order
