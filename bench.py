@@ -30,11 +30,10 @@ HBM_PEAK_GBS = 8000.0
 # grid of a hierarchy built from rho reads one density instead of three face arrays, in
 # FP64 and in the FP32 cycle alike: 4 x 4 + 3.125 + 2.125 = 21.25, plus 31.25 / 7 for
 # the coarser grids.
-VCYCLE_SCALARS_F64 = 21.25 + 31.25 / 7
-VCYCLE_SCALARS_F32 = VCYCLE_SCALARS_F64
-# FP32 cycles on grids of 256^3 and up sweep two at a time on the finest grid (p, f and
-# the density read once, p written once per pair): 2 x 4 + 3.125 + 2.125 = 13.25
-VCYCLE_SCALARS_F32_TWO = 13.25 + 31.25 / 7
+VCYCLE_SCALARS_ONE = 21.25 + 31.25 / 7
+# On grids of 256^3 and up the finest grid sweeps two at a time, FP64 and FP32 alike (p,
+# f and the density read once, p written once per pair): 2 x 4 + 3.125 + 2.125 = 13.25
+VCYCLE_SCALARS_TWO = 13.25 + 31.25 / 7
 # the same count with three face arrays on the finest grid too (31.25 x 8 / 7)
 VCYCLE_SCALARS_FACE = 31.25 * 8 / 7
 
@@ -175,21 +174,25 @@ def main():
     mg64 = r64["mg"]
     vc64 = vcycle_ms(mg64, f, mask, torch.float64)
 
-    # dominant kernel: the finest-grid smoother, timed on the stream it runs on
+    # dominant kernel: the finest-grid smoother, timed on the stream it runs on.  On grids
+    # of 256^3 and up it sweeps two at a time: four sweeps are two launches p -> t -> p, as
+    # in a cycle; below, two sweeps are two one-pass launches.
+    two64 = N >= 256
     fz = torch.zeros_like(f)
     ps = torch.zeros_like(f)
-    mg64.smooth(0, ps, fz, 2, 0)
+    sweeps = 4 if two64 else 2
+    mg64.smooth(0, ps, fz, sweeps, 0)
     torch.cuda.synchronize()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     reps = 5 if N >= 1024 else 10
     a.record()
     for _ in range(reps):
-        mg64.smooth(0, ps, fz, 2, 0)   # two one-pass sweeps, exactly as inside the V-cycle
+        mg64.smooth(0, ps, fz, sweeps, 0)
     b.record()
     torch.cuda.synchronize()
     launch_ms = a.elapsed_time(b) / (2 * reps)
-    # algorithmic bytes of one red-black sweep on the finest grid of a hierarchy built
-    # from rho: p, f and the density form of the coefficients read, p written
+    # algorithmic bytes of one launch on the finest grid of a hierarchy built from rho: p,
+    # f and the density form of the coefficients read, p written (for two sweeps or one)
     sweep_bytes = n * 8 * 4
     achieved = sweep_bytes / (launch_ms * 1e-3) / 1e9
     del fz, ps
@@ -256,7 +259,7 @@ def main():
         legs["differentiation"] = differentiation_leg(args)
         legs["rk2_projection"] = rk2_leg(256, args)
     traffic = recorded_traffic(inp.name, N)
-    scalars_f64 = VCYCLE_SCALARS_F64
+    scalars = VCYCLE_SCALARS_TWO if N >= 256 else VCYCLE_SCALARS_ONE
     out = {
         "metric": METRIC,
         "value_definition": f"grid points x V-cycles / time of the FP64 projection (setup from rho + solve to "
@@ -281,14 +284,15 @@ def main():
         "vcycle_pts_per_s": {"fp64": n / (vc64 * 1e-3), "fp32": n / (vc32 * 1e-3)},
         # algorithmic scalars per finest cell per V(2,2) cycle of the design that runs
         # (density form on the finest grid), and against the face-array count
-        "vcycle_roofline_frac": {"fp64": scalars_f64 * 8 * n / (vc64 * 1e-3) / (HBM_PEAK_GBS * 1e9),
-                                 "fp32": (VCYCLE_SCALARS_F32_TWO if N >= 256 else VCYCLE_SCALARS_F32) * 4 * n
-                                 / (vc32 * 1e-3) / (HBM_PEAK_GBS * 1e9),
+        "vcycle_roofline_frac": {"fp64": scalars * 8 * n / (vc64 * 1e-3) / (HBM_PEAK_GBS * 1e9),
+                                 "fp32": scalars * 4 * n / (vc32 * 1e-3) / (HBM_PEAK_GBS * 1e9),
                                  "fp64_face_array_count": VCYCLE_SCALARS_FACE * 8 * n / (vc64 * 1e-3)
                                  / (HBM_PEAK_GBS * 1e9),
                                  "fp32_face_array_count": VCYCLE_SCALARS_FACE * 4 * n / (vc32 * 1e-3)
                                  / (HBM_PEAK_GBS * 1e9)},
-        "roofline": {"bound": "hbm", "kernel": "rbgs_fused (finest grid, FP64 density form, one red-black sweep)",
+        "roofline": {"bound": "hbm",
+                     "kernel": ("rbgs_fused2 (finest grid, FP64 density form, two red-black sweeps per launch)"
+                                if two64 else "rbgs_fused (finest grid, FP64 density form, one red-black sweep)"),
                      "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "launch_ms": launch_ms, "bytes_per_launch": sweep_bytes},
@@ -547,7 +551,7 @@ def level_breakdown(args):
             f = f0.to(dt) if lv == 0 else torch.randn((n_l,) * 3, dtype=torch.float64, device="cuda",
                                                        generator=g).to(dt)
             ec = torch.zeros((n_l // 2,) * 3, dtype=dt, device="cuda")
-            sweeps = 2 * tm(lambda: mg.smooth(lv, p, f, 2, 0))
+            sweeps = tm(lambda: mg.smooth(lv, p, f, 4, 0))   # a cycle's four sweeps, p -> t -> ... -> p
             rr = tm(lambda: mg.residual_restrict(lv, p, f))
             pro = tm(lambda: mg.prolong_add(lv, ec, p))
             grids.append({"n": n_l, "sweeps_us": sweeps, "residual_restrict_us": rr, "prolong_us": pro,
@@ -607,11 +611,11 @@ def coarsening_sweep(args):
     return out
 
 
-TRAFFIC_KERNEL = "k_rbgs_fused<double, 128, 16, true, false>"
+TRAFFIC_KERNEL = "k_rbgs_fused2<double, false>"
 
 
 def kernel_source_hash():
-    """SHA-256 over the sources the one-pass sweep is compiled from and the hipcc flags:
+    """SHA-256 over the sources the dominant kernel is compiled from and the hipcc flags:
     recorded counter traffic is valid only for the build it was taken on."""
     import hashlib
     from paper_1410_2240_amd import build as _build
@@ -623,7 +627,7 @@ def kernel_source_hash():
     return hsh.hexdigest()
 
 
-TRAFFIC_SOURCES = ("paper_1410_2240_amd/csrc/mg_fused.hip", "paper_1410_2240_amd/csrc/mg_buffer.h",
+TRAFFIC_SOURCES = ("paper_1410_2240_amd/csrc/mg_fused2.hip", "paper_1410_2240_amd/csrc/mg_buffer.h",
                    "paper_1410_2240_amd/csrc/mg_kernels.h")
 
 

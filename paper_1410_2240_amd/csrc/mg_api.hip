@@ -141,7 +141,7 @@ long long cells(const Level& a) { return static_cast<long long>(a.n) * a.n * a.n
 // set up from rho, in its FP64 cycles and in a mixed context's FP32 cycles), 256^3 and up.
 template <typename T>
 bool two_sweep_grid(const mg_ctx* c, int l) {
-  return c->view<T>(l).rt != nullptr && mg::fused2_supported(c->lv[l].q, sizeof(T) == 8);
+  return c->view<T>(l).rt != nullptr && mg::fused2_supported(c->lv[l].q);
 }
 
 template <typename T>

@@ -317,14 +317,14 @@ __global__ __launch_bounds__(Shape<T>::TX / 2 * Shape<T>::TY) void k_rbgs_fused2
 
 }  // namespace
 
-int fused2_supported(int q, int fp64) { return (1 << q) >= (fp64 ? 256 : 256); }
+int fused2_supported(int q) { return (1 << q) >= 256; }
 
 template <typename T>
 hipError_t launch_rbgs_fused2(const T* pin, T* pout, const T* f, const T* rt, int q, double h, int order,
                               const double* fshift, int zero_in, hipStream_t s) {
   constexpr int TX = Shape<T>::TX, TY = Shape<T>::TY;
   const int n = 1 << q;
-  if (!fused2_supported(q, sizeof(T) == 8) || !rt || pin == pout) return hipErrorInvalidValue;
+  if (!fused2_supported(q) || !rt || pin == pout) return hipErrorInvalidValue;
   const long long tiles = static_cast<long long>(n / TX) * (n / TY);
   // z-chunks as long as possible while every compute unit still gets a workgroup
   int kc = n;

@@ -89,7 +89,7 @@ hipError_t launch_rbgs_half(T* p, const T* f, const T* bx, const T* by, const T*
 int fused_sweep_supported(int q);
 // Two red-black sweeps in one pass (density form, grids of 256^3 and up): pin -> pout
 // (distinct), order as launch_rbgs_fused; bit for bit two one-pass sweeps.
-int fused2_supported(int q, int fp64);
+int fused2_supported(int q);
 template <typename T>
 hipError_t launch_rbgs_fused2(const T* pin, T* pout, const T* f, const T* rt, int q, double h, int order,
                               const double* fshift, int zero_in, hipStream_t s);
