@@ -137,14 +137,25 @@ __global__ __launch_bounds__(Shape<T>::TX / 2 * Shape<T>::TY) void k_rbgs_fused2
   // plane kk into slot S; densities beyond a z wall are +inf, replaced here (not at the load)
   auto store = [&](int kk, auto s_tag) {
     constexpr int S = decltype(s_tag)::value * kSlot;
-    const bool in = kk >= 0 && kk < n;
+    if (kk >= 0 && kk < n) {   // the same for the whole workgroup: a branch, not selects
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-      if (sl[u] >= 0) {
-        Pf[S + sl[u]] = pn[u].x;
-        Pf[S + sl[u] + kWP] = pn[u].y;
-        Rf[S + sl[u]] = in ? rn[u].x : inf;
-        Rf[S + sl[u] + kWP] = in ? rn[u].y : inf;
+      for (int u = 0; u < kPer; ++u) {
+        if (sl[u] >= 0) {
+          Pf[S + sl[u]] = pn[u].x;
+          Pf[S + sl[u] + kWP] = pn[u].y;
+          Rf[S + sl[u]] = rn[u].x;
+          Rf[S + sl[u] + kWP] = rn[u].y;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        if (sl[u] >= 0) {
+          Pf[S + sl[u]] = pn[u].x;
+          Pf[S + sl[u] + kWP] = pn[u].y;
+          Rf[S + sl[u]] = inf;
+          Rf[S + sl[u] + kWP] = inf;
+        }
       }
     }
   };

@@ -15,26 +15,32 @@ namespace mg {
 // sum refined by two Newton steps r <- r + r (1 - s r), each of which squares the
 // relative error, then doubled (exact): within about an ulp of the rounded quotient
 // for sums in [1e-300, 1e300].  A density of +inf (an inactive cell, or the far side
-// of a wall) gives 0.  Every place that forms beta from densities calls this, so the
-// stored coefficients and those formed on the fly agree bit for bit.
+// of a wall) gives 0: the reciprocal of +inf is +0, and the Newton steps multiply it by
+// the sum clamped to the largest finite value (a finite sum is used as it is), which
+// keeps it +0 where the unclamped sum would make inf * 0.  Every place that forms beta
+// from densities calls this, so the stored coefficients and those formed on the fly
+// agree bit for bit.
 __device__ __forceinline__ double face_beta(double a, double b) {
   const double s = a + b;
+  const double sc = __builtin_fmin(s, __DBL_MAX__);
   double r = __builtin_amdgcn_rcp(s);
-  double e = __builtin_fma(-s, r, 1.0);
+  double e = __builtin_fma(-sc, r, 1.0);
   r = __builtin_fma(r, e, r);
-  e = __builtin_fma(-s, r, 1.0);
+  e = __builtin_fma(-sc, r, 1.0);
   r = __builtin_fma(r, e, r);
-  return __builtin_isinf(s) ? 0.0 : 2.0 * r;
+  return 2.0 * r;
 }
 
 // The FP32 face product of the mixed-precision cycles' density form: the FP32
-// reciprocal and one Newton step (within about an ulp of the rounded FP32 quotient).
+// reciprocal and one Newton step (within about an ulp of the rounded FP32 quotient),
+// +inf densities handled as in FP64.
 __device__ __forceinline__ float face_beta(float a, float b) {
   const float s = a + b;
+  const float sc = __builtin_fminf(s, __FLT_MAX__);
   float r = __builtin_amdgcn_rcpf(s);
-  const float e = __builtin_fmaf(-s, r, 1.0f);
+  const float e = __builtin_fmaf(-sc, r, 1.0f);
   r = __builtin_fmaf(r, e, r);
-  return __builtin_isinf(s) ? 0.0f : 2.0f * r;
+  return 2.0f * r;
 }
 
 // ---- setup --------------------------------------------------------------------
