@@ -1,17 +1,19 @@
 """Parity at the sizes the bench runs, in the launch configurations it times.
 
 256^3 bench field (wavy interface + ellipsoid, density form on the finest grid):
-every element of the FP64 one-pass sweep (128 x 16 tiles, 32-plane z-chunks, so with
-chunk seams), of the residual + restriction, of the prolongation and of the whole
+every element of one FP64 sweep (the one-pass kernel, 128 x 16 tiles, 32-plane
+z-chunks, so with chunk seams) and of two (the two-sweep pass, 32 x 32 tiles, 64-plane
+chunks), of the residual + restriction, of the prolongation and of the whole
 coarsened hierarchy against the oracle; FP64 kernels to <= 1e-13 max |oracle| (the
 two differ in the order of additions and in fused multiply-adds), coefficients to
 <= 1e-15.  Solutions at 128^3 and 256^3 against the oracle's multigrid solve of the
 same field, relative L2 error <= 1e-9.
 
 1024^3 Stokes crest + body (the headline workload; whole-column z-chunks): sampled
-outputs of the sweep, the residual + restriction and the prolongation, each recomputed
-by the oracle on an 8^3 window around the sample (tests/windows.py; the window rule is
-pinned against whole-grid oracle passes in tests/test_windows.py).
+outputs of one sweep, of two sweeps in one two-sweep launch, of the residual +
+restriction and of the prolongation, each recomputed by the oracle on an 8^3 window
+around the sample (12^3 for two sweeps; tests/windows.py; the window rule is pinned
+against whole-grid oracle passes in tests/test_windows.py).
 """
 import os
 from concurrent.futures import ThreadPoolExecutor
@@ -73,9 +75,10 @@ def test_hierarchy_256_matches_oracle(bench256):
 @pytest.mark.parametrize("order", [0, 1])
 @pytest.mark.parametrize("sweeps", [1, 2])
 def test_sweep_256_matches_oracle(bench256, order, sweeps):
-    """The bench's dominant launch: FP64 density-form one-pass sweep, 128 x 16 tiles,
-    32-plane z-chunks (eight chunk seams per column), both orders, one and two sweeps
-    (two sweeps alternate between p and the grid's second buffer, as in a cycle)."""
+    """The finest grid's FP64 density-form smoother in both its launches: one sweep is
+    the one-pass kernel (128 x 16 tiles, 32-plane z-chunks, eight chunk seams per
+    column), two sweeps are one launch of the two-sweep pass that every V-cycle runs
+    (32 x 32 tiles, 64-plane chunks); both orders."""
     inp, H, mg = bench256
     lev = H.fine
     g = np.random.default_rng(2560 + 2 * order + sweeps)
@@ -227,6 +230,25 @@ def test_sweep_1024_sampled_outputs_match_oracle(crest1024, order):
     print(f"1024^3 c5: sweep order={order}: oracle on {len(cells)} windows", flush=True)
     for c, gv in zip(cells, got):
         wv, scale = win.sweep_at(inp.rho, inp.mask, p, inp.f, inp.h, c, order)
+        assert abs(gv - wv) <= TOL64 * scale, (c, gv, wv)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("order", [0, 1])
+def test_two_sweeps_1024_sampled_outputs_match_oracle(crest1024, order):
+    """Two FP64 density-form sweeps of the headline grid in one launch of the two-sweep
+    pass (32 x 32 tiles, whole-column chunks, the launch the bench times), each sample
+    recomputed by the oracle's two sweeps on a 12^3 window."""
+    inp, p, rho, mask, mg = crest1024
+    print(f"1024^3 c5: two sweeps order={order}: GPU", flush=True)
+    out = mg.smooth(0, dev(p), dev(inp.f), 2, order)
+    cells = sample_cells(inp, np.random.default_rng(10260 + order))
+    got = win.gather(out, cells)
+    del out
+    torch.cuda.empty_cache()
+    print(f"1024^3 c5: two sweeps order={order}: oracle on {len(cells)} windows", flush=True)
+    for c, gv in zip(cells, got):
+        wv, scale = win.sweep_at(inp.rho, inp.mask, p, inp.f, inp.h, c, order, sweeps=2)
         assert abs(gv - wv) <= TOL64 * scale, (c, gv, wv)
 
 

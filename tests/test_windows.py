@@ -1,6 +1,6 @@
 """Pin of the window rule of tests/windows.py: the oracle's value at a sampled cell from
 an 8^3 window equals the whole-grid oracle's value there, for one red-black sweep in
-either order, the residual + 8-child restriction and the trilinear prolongation, at
+either order (two sweeps from a 12^3 window), the residual + 8-child restriction and the trilinear prolongation, at
 random cells, on both z walls, across the periodic wrap in x and y and next to the body
 (32^3 Stokes-crest field with its droplets, bubbles and the ellipsoid)."""
 import numpy as np
@@ -27,12 +27,13 @@ def crest():
     return inp, H, p, f, e, cells
 
 
+@pytest.mark.parametrize("sweeps", [1, 2])
 @pytest.mark.parametrize("order", [0, 1])
-def test_sweep_window(crest, order):
+def test_sweep_window(crest, order, sweeps):
     inp, H, p, f, e, cells = crest
-    whole = omg.smooth(p, f, H.fine, 1, (omg.RED, omg.BLACK) if order == 0 else (omg.BLACK, omg.RED))
+    whole = omg.smooth(p, f, H.fine, sweeps, (omg.RED, omg.BLACK) if order == 0 else (omg.BLACK, omg.RED))
     for c in cells:
-        v, _ = win.sweep_at(inp.rho, inp.mask, p, f, inp.h, c, order)
+        v, _ = win.sweep_at(inp.rho, inp.mask, p, f, inp.h, c, order, sweeps)
         assert v == whole[c], c
 
 

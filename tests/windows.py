@@ -1,6 +1,7 @@
 """Small windows of a large grid, for checking sampled outputs with the oracle.
 
-One red-black sweep changes a cell from values at most two cells away, a residual from
+One red-black sweep changes a cell from values at most two cells away (two sweeps: four),
+a residual from
 values one cell away, and an 8-child restriction or a trilinear prolongation from one
 coarse cell around the parent.  So the oracle can recompute a sampled output of a
 1024^3 pass on an 8^3 window around the sample, with the window's own (wrong) edges
@@ -65,15 +66,17 @@ def _level(rho, mask, h):
     return lev
 
 
-def sweep_at(rho, mask, p, f, h, cell, order):
+def sweep_at(rho, mask, p, f, h, cell, order, sweeps=1):
     """The oracle's value at `cell` after one red-black sweep (order 0: red then black)
-    of the whole grid, from an 8^3 window; returns (value, scale of the window)."""
+    of the whole grid, from an 8^3 window, or after two sweeps from a 12^3 window (each
+    sweep reaches two cells further); returns (value, scale of the window)."""
     from oracle import multigrid as omg
     N = rho.shape[-1]
-    o = origin(N, *cell)
-    lev = _level(cut(rho, o), cut(mask, o), h)
-    pw = cut(p, o)
-    out = omg.smooth(pw, cut(f, o), lev, 1, (omg.RED, omg.BLACK) if order == 0 else (omg.BLACK, omg.RED))
+    w = 4 * sweeps + 4
+    o = origin(N, *cell, w=w)
+    lev = _level(cut(rho, o, w), cut(mask, o, w), h)
+    pw = cut(p, o, w)
+    out = omg.smooth(pw, cut(f, o, w), lev, sweeps, (omg.RED, omg.BLACK) if order == 0 else (omg.BLACK, omg.RED))
     return out[local(o, N, *cell)], max(np.abs(out).max(), np.abs(pw).max())
 
 
