@@ -398,6 +398,177 @@ __global__ __launch_bounds__(kMarchThreads) void k_residual_march(MarchArgs<T> a
   }
 }
 
+// RESTRICT on the density form (128 x 8 tiles), with the in-plane neighbours of every
+// plane exchanged through LDS instead of read again from the caches.  A thread loads its
+// pair's two rows of p and rt, plus its share of the plane's halo (the rows j0-1 and
+// j0+8 and the x neighbours of the tile rows), one plane before they are needed (f in
+// the step that uses it); at the
+// start of step k it puts plane k+1 into one of two LDS planes, and after that step's
+// barrier everyone reads plane k from the other.  Each line of p and rt is then fetched
+// once per tile plane, the halo once more, however little of one step stays in L2.
+// The faces, sums and restriction are those of k_residual_march, so the bits are too.
+template <typename T>
+__global__ __launch_bounds__(kMarchThreads) void k_restrict_lds(MarchArgs<T> a) {
+  using V2 = typename Vec2<T>::type;
+  constexpr int TX = 128, PAIRS = TX / 2, RP = kMarchThreads / PAIRS, TY = 2 * RP;
+  constexpr int LW = TX + 2, LH = TY + 2;   // a staged plane: the tile and a 1-cell halo
+  __shared__ T Lp[2][LH][LW];
+  __shared__ T Lr[2][LH][LW];
+  const int q = a.q, n = 1 << q;
+  const T inf = __builtin_huge_val();
+  const T zero = T(0);
+  const int tid = threadIdx.x;
+  const int G = gridDim.x, bid = blockIdx.x;
+  const int lid = (G % 8 == 0) ? (bid % 8) * (G / 8) + bid / 8 : bid;   // neighbours on one XCD
+  const int ntx = n / TX, nty = n / TY;
+  const int i0 = (lid % ntx) * TX;
+  const int j0 = ((lid / ntx) % nty) * TY;
+  const int k0 = (lid / (ntx * nty)) * a.kc;
+  const int xt = tid % PAIRS, rp = tid / PAIRS;
+  const int ip = i0 + 2 * xt;
+  const int ja = j0 + 2 * rp, jb = ja + 1;
+  const unsigned oa = off_of<T>(ip, ja, q), ob = off_of<T>(ip, jb, q);
+  const int ra_ = 1 + 2 * rp, rb_ = ra_ + 1, cc = 1 + 2 * xt;   // the pair in a staged plane
+  const T fs = a.fshift ? static_cast<T>(*a.fshift) : zero;
+  // halo share: threads 0 .. 63 a pair of row j0-1, 64 .. 127 a pair of row j0+TY,
+  // 128 .. 128+2TY-1 the cell left or right of a tile row
+  int hr = -1, hc = 0;
+  bool hpair = false;
+  unsigned ho = 0;
+  if (tid < 2 * PAIRS) {
+    hpair = true;
+    hr = tid < PAIRS ? 0 : LH - 1;
+    hc = 1 + 2 * (tid % PAIRS);
+    ho = off_of<T>(i0 + 2 * (tid % PAIRS), j0 - 1 + hr, q);
+  } else if (tid < 2 * PAIRS + 2 * TY) {
+    const int e = tid - 2 * PAIRS;
+    hr = 1 + e / 2;
+    hc = (e & 1) ? LW - 1 : 0;
+    ho = off_of<T>((e & 1) ? i0 + TX : i0 - 1, j0 - 1 + hr, q);
+  }
+  // one plane's loads: the pair's rows of p and rt, and the halo share
+  struct Plane {
+    V2 pa, pb, ra, rb, hp, hrt;
+  };
+  auto load = [&](int kk) {
+    const Rsrc pk = plane_rsrc(a.p, kk, q), rk = plane_rsrc(a.rt, kk, q);
+    Plane L;
+    L.pa = ld2(pk, oa, zero);
+    L.pb = ld2(pk, ob, zero);
+    L.ra = ld2(rk, oa, zero);
+    L.rb = ld2(rk, ob, zero);
+    L.hp = V2{zero, zero};
+    L.hrt = V2{zero, zero};
+    if (hpair) {
+      L.hp = ld2(pk, ho, zero);
+      L.hrt = ld2(rk, ho, zero);
+    } else if (hr >= 0) {
+      L.hp.x = ld1(pk, ho, zero);
+      L.hrt.x = ld1(rk, ho, zero);
+    }
+    return L;
+  };
+  auto put = [&](int b, const Plane& L) {
+    Lp[b][ra_][cc] = L.pa.x;
+    Lp[b][ra_][cc + 1] = L.pa.y;
+    Lp[b][rb_][cc] = L.pb.x;
+    Lp[b][rb_][cc + 1] = L.pb.y;
+    Lr[b][ra_][cc] = L.ra.x;
+    Lr[b][ra_][cc + 1] = L.ra.y;
+    Lr[b][rb_][cc] = L.rb.x;
+    Lr[b][rb_][cc + 1] = L.rb.y;
+    if (hpair) {
+      Lp[b][hr][hc] = L.hp.x;
+      Lp[b][hr][hc + 1] = L.hp.y;
+      Lr[b][hr][hc] = L.hrt.x;
+      Lr[b][hr][hc + 1] = L.hrt.y;
+    } else if (hr >= 0) {
+      Lp[b][hr][hc] = L.hp.x;
+      Lr[b][hr][hc] = L.hrt.x;
+    }
+  };
+  auto load_f = [&](int kk, V2& fa, V2& fb) {
+    const Rsrc fk = plane_rsrc(a.f, kk, q);
+    fa = ld2(fk, oa, zero);
+    fb = ld2(fk, ob, zero);
+  };
+
+  // prologue: plane k0 staged; the pair's p on k0-1, rt faces to plane k0-1; plane k0+1
+  // and f of k0 loaded
+  Plane cur = load(k0);
+  const Rsrc p_lo = plane_rsrc(a.p, k0 - 1, q), r_lo = plane_rsrc(a.rt, k0 - 1, q);
+  V2 pa_lo = ld2(p_lo, oa, zero), pb_lo = ld2(p_lo, ob, zero);
+  const V2 la = ld2(r_lo, oa, zero), lb = ld2(r_lo, ob, zero);
+  Plane nxt = load(k0 + 1);
+  put(k0 & 1, cur);
+  const bool in_lo = k0 >= 1;
+  V2 za = in_lo ? V2{face_beta(la.x, cur.ra.x), face_beta(la.y, cur.ra.y)} : V2{zero, zero};
+  V2 zb = in_lo ? V2{face_beta(lb.x, cur.rb.x), face_beta(lb.y, cur.rb.y)} : V2{zero, zero};
+  T csum = zero;
+  for (int k = k0; k < k0 + a.kc; ++k) {
+    __syncthreads();   // plane k staged; the other LDS plane no longer read
+    put((k + 1) & 1, nxt);
+    const Plane hi = nxt;   // the pair's p and rt on plane k+1
+    nxt = load(k + 2);
+    V2 fa, fb;
+    load_f(k, fa, fb);
+    // plane k's neighbours of the pair, from LDS
+    const int b = k & 1;
+    const V2 pd{Lp[b][ra_ - 1][cc], Lp[b][ra_ - 1][cc + 1]}, pup{Lp[b][rb_ + 1][cc], Lp[b][rb_ + 1][cc + 1]};
+    const T pla = Lp[b][ra_][cc - 1], pra = Lp[b][ra_][cc + 2];
+    const T plb = Lp[b][rb_][cc - 1], prb = Lp[b][rb_][cc + 2];
+    const V2 rd{Lr[b][ra_ - 1][cc], Lr[b][ra_ - 1][cc + 1]}, rup2{Lr[b][rb_ + 1][cc], Lr[b][rb_ + 1][cc + 1]};
+    const T rla = Lr[b][ra_][cc - 1], rra = Lr[b][ra_][cc + 2];
+    const T rlb = Lr[b][rb_][cc - 1], rrb = Lr[b][rb_][cc + 2];
+    const bool in_hi = k + 1 < n;
+    const V2 ha_i{in_hi ? hi.ra.x : inf, in_hi ? hi.ra.y : inf}, hb_i{in_hi ? hi.rb.x : inf, in_hi ? hi.rb.y : inf};
+    const V2 ra = cur.ra, rb = cur.rb;
+    PF<T> Fa, Fb;
+    const T mid0 = face_beta(ra.x, rb.x), mid1 = face_beta(ra.y, rb.y);   // between rows a and b
+    Fa.x0 = face_beta(rla, ra.x);
+    Fa.x1 = face_beta(ra.x, ra.y);
+    Fa.x2 = face_beta(ra.y, rra);
+    Fa.ym0 = face_beta(rd.x, ra.x);
+    Fa.ym1 = face_beta(rd.y, ra.y);
+    Fa.yp0 = mid0;
+    Fa.yp1 = mid1;
+    Fa.zm0 = za.x;
+    Fa.zm1 = za.y;
+    Fa.zp0 = face_beta(ra.x, ha_i.x);
+    Fa.zp1 = face_beta(ra.y, ha_i.y);
+    Fb.x0 = face_beta(rlb, rb.x);
+    Fb.x1 = face_beta(rb.x, rb.y);
+    Fb.x2 = face_beta(rb.y, rrb);
+    Fb.ym0 = mid0;
+    Fb.ym1 = mid1;
+    Fb.yp0 = face_beta(rb.x, rup2.x);
+    Fb.yp1 = face_beta(rb.y, rup2.y);
+    Fb.zm0 = zb.x;
+    Fb.zm1 = zb.y;
+    Fb.zp0 = face_beta(rb.x, hb_i.x);
+    Fb.zp1 = face_beta(rb.y, hb_i.y);
+    T r0a, r1a, r0b, r1b;
+    pair_r(Fa, cur.pa, pla, pra, pd, cur.pb, pa_lo, hi.pa, fa, fs, a.inv_h2, r0a, r1a);
+    pair_r(Fb, cur.pb, plb, prb, cur.pa, pup, pb_lo, hi.pb, fb, fs, a.inv_h2, r0b, r1b);
+    // children in the order of every other restriction: (row a, plane 2K),
+    // (row b, plane 2K), (row a, plane 2K+1), (row b, plane 2K+1)
+    if ((k & 1) == 0) csum = zero;
+    csum += r0a + r1a;
+    csum += r0b + r1b;
+    if (k & 1) {
+      const int qc = q - 1;
+      const int C = ((((k >> 1) << qc) | (ja >> 1)) << qc) | (ip >> 1);
+      a.fc[C] = csum * T(0.125);
+      a.ec[C] = zero;
+    }
+    pa_lo = cur.pa;
+    pb_lo = cur.pb;
+    za = V2{Fa.zp0, Fa.zp1};
+    zb = V2{Fb.zp0, Fb.zp1};
+    cur = hi;
+  }
+}
+
 template <typename T, bool RHO, int MODE>
 hipError_t launch_mode(MarchArgs<T> a, int* nblocks, hipStream_t s) {
   const int n = 1 << a.q;
@@ -469,6 +640,16 @@ hipError_t launch_residual_restrict_march(const T* p, const T* f, const T* bx, c
   a.fc = fc;
   a.ec = ec;
   int nb = 0;
+  if (rt && (1 << q) >= 128) {   // the density form: neighbours through LDS
+    const int n = 1 << q;
+    const long long tiles = static_cast<long long>(n / 128) * (n / 8);
+    int kc = 64;
+    while (kc > 2 && tiles * (n / kc) < 1024) kc /= 2;
+    if (kc > n) kc = n;
+    a.kc = kc;
+    hipLaunchKernelGGL(k_restrict_lds<T>, dim3(static_cast<unsigned>(tiles * (n / kc))), dim3(kMarchThreads), 0, s, a);
+    return hipGetLastError();
+  }
   return launch_form<kModeRestrict>(a, &nb, s);
 }
 
