@@ -72,11 +72,16 @@ enum {
                     and dot products FP64.  Removes the few error modes a V-cycle misses
                     at steep, non-grid-aligned density interfaces.  Four more FP64
                     finest-grid vectors in the workspace. */
-  MG_COARSEN_DENSITY = 4 /* mg_setup_from_rho only: the coarsening section 3.1 rejects -
+  MG_COARSEN_DENSITY = 4, /* mg_setup_from_rho only: the coarsening section 3.1 rejects -
                     density restricted cell centre to cell centre (mean over active
                     children), open areas restricted separately (mean of 4 faces), and
                     beta = area * 2/(rho_L + rho_R) re-formed on every grid.  The finest
                     operator is unchanged; for comparison with the default. */
+  MG_FROM_RHO = 8 /* mg_workspace_size and mg_setup_from_rho only (pass the same flags to
+                    both): the workspace is for a setup from the density, so an MG_MIXED
+                    context on a grid of 64^3 and up leaves out the FP32 face arrays of its
+                    finest grid, which its FP32 cycles form from the density instead (12
+                    bytes per cell less).  Without it the size covers both setups. */
 };
 
 /* precision selector of the component entry points */

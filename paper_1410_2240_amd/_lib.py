@@ -12,7 +12,7 @@ import os
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmgpoisson.so")
 
 MG_OK, MG_EINVAL, MG_EWORKSPACE, MG_EHIP, MG_ENOCONV, MG_EBREAKDOWN = 0, -1, -2, -3, -4, -5
-MG_FP64, MG_MIXED, MG_KRYLOV, MG_COARSEN_DENSITY = 0, 1, 2, 4
+MG_FP64, MG_MIXED, MG_KRYLOV, MG_COARSEN_DENSITY, MG_FROM_RHO = 0, 1, 2, 4, 8
 MG_PREC_F64, MG_PREC_F32 = 0, 1
 MG_PRE, MG_POST = 0, 1
 MG_MAX_LANES = 16

@@ -575,9 +575,11 @@ int setup_impl(mg_ctx** out, void* workspace, size_t ws_bytes, const double* bx,
   if (mg::validate_dims(dims, &n) != 0) return fail(MG_EINVAL, "dims must be equal powers of two in [8, 1024]");
   if (!mask || (!rho && (!bx || !by || !bz))) return fail(MG_EINVAL, "null array pointer");
   if (!(h > 0.0) || !std::isfinite(h)) return fail(MG_EINVAL, "h must be positive and finite");
-  if (flags < 0 || flags > (MG_MIXED | MG_KRYLOV | MG_COARSEN_DENSITY)) return fail(MG_EINVAL, "unknown flags %d", flags);
+  if (flags < 0 || flags > (MG_MIXED | MG_KRYLOV | MG_COARSEN_DENSITY | MG_FROM_RHO))
+    return fail(MG_EINVAL, "unknown flags %d", flags);
   const bool density = (flags & MG_COARSEN_DENSITY) != 0;
   if (density && !rho) return fail(MG_EINVAL, "density coarsening needs the cell density (mg_setup_from_rho)");
+  if ((flags & MG_FROM_RHO) && !rho) return fail(MG_EINVAL, "MG_FROM_RHO is for mg_setup_from_rho");
   mg::Plan plan;
   if (mg::build_plan(n, flags, &plan) != 0) return fail(MG_EINVAL, "unsupported grid");
   if (!workspace) return fail(MG_EWORKSPACE, "null workspace");
@@ -660,9 +662,10 @@ int setup_impl(mg_ctx** out, void* workspace, size_t ws_bytes, const double* bx,
     hip(mg::launch_setup_fine(bx, by, bz, mask, f0.q, f0.bx, f0.by, f0.bz, f0.mask, c->counters, s), "setup_fine");
   }
   if (rho) {
-    if ((flags & MG_MIXED) && mg::fused_sweep_supported(f0.q)) {
+    if (plan.lv[0].rt32 != mg::kAbsent) {
       // the FP32 cycles form their finest faces from an FP32 copy (one-pass sweep grids,
       // so that smoother and residual use the same FP32 operator)
+      if (!mg::fused_sweep_supported(f0.q)) return cleanup(fail(MG_EINVAL, "internal: FP32 density copy below 64^3"));
       f0.rt32 = at<float>(c->ws, plan.lv[0].rt32);
       hip(mg::launch_to_f32(f0.rt, f0.rt32, cells(f0), s), "to_f32(rt)");
     }

@@ -31,8 +31,9 @@ int validate_dims(const int dims[3], int* n_out) {
 int build_plan(int n, int flags, Plan* plan) {
   const int d[3] = {n, n, n};
   if (validate_dims(d, nullptr) != 0 || !plan) return -1;
-  if (flags < 0 || flags > (kFlagMixed | kFlagKrylov | kFlagDensity)) return -1;
+  if (flags < 0 || flags > (kFlagMixed | kFlagKrylov | kFlagDensity | kFlagFromRho)) return -1;
   const bool mixed = (flags & kFlagMixed) != 0;
+  const bool density32 = mixed && n >= kDensity32MinN;   // the finest grid's FP32 density copy
   Plan p;
   p.n = n;
   p.flags = flags;
@@ -58,13 +59,17 @@ int build_plan(int n, int flags, Plan* plan) {
     // finest grid: the density form of the face coefficients (hierarchies built from rho)
     lv.rt = l == 0 ? c.take(cells * 8) : kAbsent;
     if (mixed) {
-      lv.bx32 = c.take(cells * 4);
-      lv.by32 = c.take(cells * 4);
-      lv.bz32 = c.take(cells * 4);
+      if (l == 0 && density32 && (flags & kFlagFromRho)) {
+        lv.bx32 = lv.by32 = lv.bz32 = kAbsent;
+      } else {
+        lv.bx32 = c.take(cells * 4);
+        lv.by32 = c.take(cells * 4);
+        lv.bz32 = c.take(cells * 4);
+      }
       lv.f32 = c.take(cells * 4);   // level 0: the FP32 residual of each refinement step
       lv.e32 = c.take(cells * 4);
       lv.t32 = c.take(cells * 4);
-      lv.rt32 = l == 0 ? c.take(cells * 4) : kAbsent;
+      lv.rt32 = l == 0 && density32 ? c.take(cells * 4) : kAbsent;
     } else {
       lv.bx32 = lv.by32 = lv.bz32 = lv.f32 = lv.e32 = lv.t32 = kAbsent;
     }

@@ -18,7 +18,11 @@ constexpr int kMaxLevels = 10;        // 1024 -> 4
 constexpr int kNumPartials = 16384;   // blocks of the two-pass reductions
 constexpr size_t kAlign = 256;
 constexpr int kPartialSets = 4;       // reductions that may be in flight together
-constexpr int kFlagMixed = 1, kFlagKrylov = 2, kFlagDensity = 4;
+constexpr int kFlagMixed = 1, kFlagKrylov = 2, kFlagDensity = 4, kFlagFromRho = 8;
+// A mixed hierarchy's finest grid of this size and up keeps an FP32 copy of the density
+// (the grids its one-pass and two-pass sweeps run on), from which the FP32 cycles form
+// their finest faces; with kFlagFromRho it has no FP32 face arrays.
+constexpr int kDensity32MinN = 64;
 
 constexpr size_t kAbsent = static_cast<size_t>(-1);
 
@@ -56,8 +60,8 @@ struct Plan {
 int validate_dims(const int dims[3], int* n_out);
 
 // Fills `plan` for an N^3 grid and flags (bit 0 mixed precision, bit 1 flexible CG,
-// bit 2 density coarsening, which needs no extra storage);
-// returns 0, or -1 for unsupported N or flags.
+// bit 2 density coarsening, which needs no extra storage, bit 3 a setup from the
+// density); returns 0, or -1 for unsupported N or flags.
 int build_plan(int n, int flags, Plan* plan);
 
 // The arrays one solve writes (every grid's right-hand side, correction and second

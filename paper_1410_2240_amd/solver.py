@@ -12,7 +12,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import (MG_COARSEN_DENSITY, MG_EBREAKDOWN, MG_ENOCONV, MG_FP64, MG_KRYLOV, MG_MIXED, MG_OK,
+from ._lib import (MG_COARSEN_DENSITY, MG_EBREAKDOWN, MG_ENOCONV, MG_FP64, MG_FROM_RHO, MG_KRYLOV, MG_MIXED, MG_OK,
                    MG_POST, MG_PRE, MG_PREC_F32, MG_PREC_F64, MgStats)
 
 
@@ -87,7 +87,8 @@ class MG:
         self.mixed = bool(mixed)
         self.krylov = bool(krylov)
         self.device = ref.device
-        flags = _flags(mixed, krylov) | (MG_COARSEN_DENSITY if _density_coarsening else 0)
+        flags = (_flags(mixed, krylov) | (MG_COARSEN_DENSITY if _density_coarsening else 0)
+                 | (MG_FROM_RHO if _rho is not None else 0))
         size = lib.mg_workspace_size(_lib.dims3(n), flags)
         if size == 0:
             raise ValueError(f"unsupported grid {n}^3")

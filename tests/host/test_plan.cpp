@@ -51,8 +51,14 @@ static void check_layout(int n, int flags) {
       CHECK(a.f == mg::kAbsent && a.e == mg::kAbsent);
     }
     if (flags & 1) {
-      for (size_t o : {a.bx32, a.by32, a.bz32, a.f32, a.e32, a.t32}) spans.push_back({o, c * 4});
-      if (l == 0) spans.push_back({a.rt32, c * 4});
+      const bool dens32 = l == 0 && n >= mg::kDensity32MinN;   // the finest grid's FP32 density copy
+      if (dens32 && (flags & mg::kFlagFromRho)) {   // a setup from rho: no FP32 finest faces
+        CHECK(a.bx32 == mg::kAbsent && a.by32 == mg::kAbsent && a.bz32 == mg::kAbsent);
+      } else {
+        for (size_t o : {a.bx32, a.by32, a.bz32}) spans.push_back({o, c * 4});
+      }
+      for (size_t o : {a.f32, a.e32, a.t32}) spans.push_back({o, c * 4});
+      if (dens32) spans.push_back({a.rt32, c * 4});
       else CHECK(a.rt32 == mg::kAbsent);
     } else {
       CHECK(a.bx32 == mg::kAbsent && a.f32 == mg::kAbsent);
@@ -133,15 +139,26 @@ int main() {
   for (const auto& d : bad) CHECK(mg::validate_dims(d, nullptr) != 0);
   CHECK(mg::validate_dims(nullptr, nullptr) != 0);
   mg::Plan p;
-  CHECK(mg::build_plan(64, 8, &p) != 0);
+  CHECK(mg::build_plan(64, 16, &p) != 0);
   CHECK(mg::build_plan(64, -1, &p) != 0);
   for (int m : {8, 16, 64, 256})
-    for (int fl : {0, 1, 2, 3}) {
+    for (int fl : {0, 1, 2, 3, 8, 9, 10, 11}) {
       check_layout(m, fl);
       check_lane_layout(m, fl);
     }
   CHECK(mg::build_lane_plan(48, 0, &p) != 0);
-  CHECK(mg::build_lane_plan(64, 8, &p) != 0);
+  CHECK(mg::build_lane_plan(64, 16, &p) != 0);
+  // a mixed setup from rho on a grid of 64^3 and up leaves out the FP32 finest faces
+  {
+    mg::Plan pa, pb;
+    for (int m : {64, 1024}) {
+      CHECK(mg::build_plan(m, 1, &pa) == 0 && mg::build_plan(m, 1 | 8, &pb) == 0);
+      const size_t faces = 3 * static_cast<size_t>(m) * m * m * 4;
+      CHECK(pa.total - pb.total >= faces && pa.total - pb.total < faces + 3 * mg::kAlign);
+    }
+    CHECK(mg::build_plan(32, 1, &pa) == 0 && mg::build_plan(32, 1 | 8, &pb) == 0 && pa.total == pb.total);
+    CHECK(mg::build_plan(256, 8, &pa) == 0 && mg::build_plan(256, 0, &pb) == 0 && pa.total == pb.total);
+  }
   // density coarsening needs no storage of its own
   {
     mg::Plan pa, pb;

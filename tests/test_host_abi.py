@@ -49,15 +49,17 @@ def test_workspace_size_is_host_arithmetic():
     assert s32 - s64 > n * 6 * 4
     assert lib.mg_workspace_size(_lib.dims3(48), 0) == 0
     assert lib.mg_workspace_size((ctypes.c_int * 3)(64, 64, 32), 0) == 0
-    assert lib.mg_workspace_size(_lib.dims3(64), 8) == 0
+    assert lib.mg_workspace_size(_lib.dims3(64), 16) == 0
     assert lib.mg_workspace_size(_lib.dims3(64), 4) == lib.mg_workspace_size(_lib.dims3(64), 0)
+    # a mixed setup from the density leaves out the FP32 face arrays of the finest grid
+    assert s32 - lib.mg_workspace_size(_lib.dims3(256), 1 | _lib.MG_FROM_RHO) >= 3 * n * 4
     # one concurrent right-hand side's scratch: every grid's f, e and second buffer
     # (the finest grid's f and e are the caller's), without the coefficients
     lane = lib.mg_lane_workspace_size(_lib.dims3(256), 0)
     assert n * 8 < lane < n * 8 * (1 + 3 / 7 + 0.01) + (1 << 20)
     assert lib.mg_lane_workspace_size(_lib.dims3(256), 2) - lane >= 4 * n * 8
     assert lib.mg_lane_workspace_size(_lib.dims3(48), 0) == 0
-    assert lib.mg_lane_workspace_size(_lib.dims3(64), 8) == 0
+    assert lib.mg_lane_workspace_size(_lib.dims3(64), 16) == 0
 
 
 def test_invalid_arguments_rejected_on_the_host():
@@ -79,7 +81,11 @@ def test_invalid_arguments_rejected_on_the_host():
     assert lib.mg_merge_fill(None, fake, good, None) == _lib.MG_EINVAL
     assert lib.mg_coeffs_from_rho(fake, fake, bad, fake, fake, fake, None) == _lib.MG_EINVAL
     ctx = ctypes.c_void_p()
-    assert lib.mg_setup_from_rho(ctypes.byref(ctx), fake, 1 << 20, fake, fake, good, 1.0 / 32, 8, None) == _lib.MG_EINVAL
+    assert lib.mg_setup_from_rho(ctypes.byref(ctx), fake, 1 << 20, fake, fake, good, 1.0 / 32, 16, None) == _lib.MG_EINVAL
+    # the layout flag of a setup from the density is no flag of a setup from face arrays
+    assert lib.mg_setup(ctypes.byref(ctx), fake, 1 << 20, fake, fake, fake, fake, good, 1.0 / 32, _lib.MG_FROM_RHO,
+                        None) == _lib.MG_EINVAL
+    assert "MG_FROM_RHO" in _lib.last_error()
     assert lib.mg_setup_from_rho(ctypes.byref(ctx), fake, 16, fake, fake, good, 1.0 / 32, 0, None) == _lib.MG_EWORKSPACE
     assert not ctx.value
     assert lib.mg_add_lanes(None, fake, 1 << 20, 1) == _lib.MG_EINVAL
