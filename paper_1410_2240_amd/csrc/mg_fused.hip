@@ -333,7 +333,6 @@ __global__ __launch_bounds__(TX / 2 * TY) void k_rbgs_fused(const T* __restrict_
   const int j0 = ((lid / ntx) % nty) * TY;
   const int k0 = (lid / (ntx * nty)) * kc;
   const int k1 = k0 + kc;
-  const int second = 1 - first;
   const T fs = fshift ? static_cast<T>(*fshift) : T(0);
   // A step branches on the colour parity of the thread's row, and contains barriers:
   // every wave must hold rows of one parity.  A wave spans R = 64 / (TX/2) rows (R = 1
