@@ -535,3 +535,39 @@ def test_fcg_on_a_workspace_of_nan_patterns(N, mixed):
         assert rc == 0, (fill, rc, _lib.last_error())
         out.append((host(p), hist[:nh[0]].copy()))
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+@pytest.mark.parametrize("krylov", [False, True])
+def test_from_rho_workspace_gives_the_same_bits(krylov):
+    """MG_FROM_RHO leaves the FP32 face arrays of the finest grid out of a mixed
+    workspace (the FP32 cycles form those faces from the density).  A mixed solve on a
+    workspace sized and set up with the flag, filled with NaN bit patterns, equals bit
+    for bit the solve on a workspace sized without it (128^3: one-pass sweeps and the
+    z-marching passes on the FP32 density copy; both outer iterations)."""
+    import ctypes
+    from paper_1410_2240_amd import _lib
+    lib = _lib.load()
+    N = 128
+    inp, _ = workload("c2", N)
+    rho, mask, f = dev(inp.rho), dev(inp.mask), dev(inp.f)
+    base = _lib.MG_MIXED | (_lib.MG_KRYLOV if krylov else 0)
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    sizes = [lib.mg_workspace_size(_lib.dims3(N), fl) for fl in (base, base | _lib.MG_FROM_RHO)]
+    assert sizes[0] - sizes[1] >= 3 * N ** 3 * 4
+    out = []
+    for flags, size in zip((base, base | _lib.MG_FROM_RHO), sizes):
+        ws = torch.full((size,), 0xFF, dtype=torch.uint8, device="cuda")
+        ctx = ctypes.c_void_p()
+        assert lib.mg_setup_from_rho(ctypes.byref(ctx), ctypes.c_void_p(ws.data_ptr()), size,
+                                     ctypes.c_void_p(rho.data_ptr()), ctypes.c_void_p(mask.data_ptr()),
+                                     _lib.dims3(N), 1.0 / N, flags, stream) == 0, _lib.last_error()
+        p = torch.zeros_like(f)
+        hist = np.zeros(101)
+        nh = (ctypes.c_int * 1)()
+        rc = lib.mg_solve(ctx, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(p.data_ptr()), 1, 1e-10, 100,
+                          hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), nh, None)
+        lib.mg_destroy(ctx)
+        assert rc == 0, (flags, rc, _lib.last_error())
+        out.append((host(p), hist[:nh[0]].copy()))
+        del ws
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
