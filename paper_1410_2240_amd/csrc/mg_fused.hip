@@ -295,7 +295,7 @@ __device__ __forceinline__ void gs(T (*cur)[2][W / 2], int r, int c, T lo, T hi,
     // the coefficients come in
     const T S = fmad(C.zp, hi, fmad(C.zm, lo, fmad(C.yp, at<T, W>(cur, r + 1, c), fmad(C.ym, at<T, W>(cur, r - 1, c),
                 fmad(C.xp, at<T, W>(cur, r, c + 1), C.xm * at<T, W>(cur, r, c - 1))))));
-    at<T, W>(cur, r, c) = fmad(-h2, C.f - fs, S) / D;
+    at<T, W>(cur, r, c) = gs_quotient(fmad(-h2, C.f - fs, S), D);
   }
 }
 

@@ -228,7 +228,7 @@ __global__ __launch_bounds__(Shape<T>::TX / 2 * Shape<T>::TY) void k_rbgs_fused2
     if (D > T(0)) {
       const T Sv = fma_t(F.zp, Pf[SA + x.own], fma_t(F.zm, lo_p, fma_t(F.yp, Pf[S + x.own + kRow],
                    fma_t(F.ym, Pf[S + x.own - kRow], fma_t(F.xp, Pf[S + x.left + 1], F.xm * Pf[S + x.left])))));
-      Pf[S + x.own] = fma_t(-h2, fv - fs, Sv) / D;
+      Pf[S + x.own] = gs_quotient(fma_t(-h2, fv - fs, Sv), D);
     }
   };
 

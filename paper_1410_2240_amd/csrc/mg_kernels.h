@@ -43,6 +43,20 @@ __device__ __forceinline__ float face_beta(float a, float b) {
   return 2.0f * r;
 }
 
+// The quotient of a Gauss-Seidel update, numerator over the diagonal D > 0 (a sum of at
+// most six face products, far from the ends of the range).  FP64: the correctly rounded
+// quotient.  FP32 (the cycles of a mixed-precision solve, whose result only corrects an
+// FP64 iterate): the reciprocal of D, the product, and one correction from the exact
+// remainder n - D q, within an ulp of the rounded quotient in four instructions where the
+// IEEE division takes about ten.  Every FP32 sweep on the one-pass and two-sweep paths
+// uses it, so they stay bit for bit the same.
+__device__ __forceinline__ double gs_quotient(double n, double d) { return n / d; }
+__device__ __forceinline__ float gs_quotient(float n, float d) {
+  const float r = __builtin_amdgcn_rcpf(d);
+  const float q = n * r;
+  return __builtin_fmaf(__builtin_fmaf(-d, q, n), r, q);
+}
+
 // ---- setup --------------------------------------------------------------------
 // beta_f = o_f 2/(rho_L + rho_R); with rho == nullptr the open-face areas o_f (0 or 1)
 hipError_t launch_coeffs_from_rho(const double* rho, const uint8_t* mask, int q,
