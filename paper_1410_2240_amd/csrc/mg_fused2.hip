@@ -222,6 +222,18 @@ __global__ __launch_bounds__(Shape<T>::TX / 2 * Shape<T>::TY) void k_rbgs_fused2
                  face_beta(Rf[S + x.own - kRow], rc), face_beta(rc, Rf[S + x.own + kRow]),
                  face_beta(lo_r, rc), face_beta(rc, Rf[SA + x.own])};
   };
+  // The B1 update's z faces are those of A1 in the same column: on the plane above in
+  // this step (its face below) and on the plane below two steps earlier (its face
+  // above), formed from the same densities in the same order.  A1's faces are formed
+  // whenever its column is worked on, also where its update is out of bounds (planes
+  // beyond a wall hold +inf densities, which give faces of 0), so both are there
+  // whenever B1 runs.
+  auto faces_b1 = [&](auto s_tag, const Cell& x, T zm, T zp) {
+    constexpr int S = decltype(s_tag)::value * kSlot;
+    const T rc = Rf[S + x.own];
+    return Faces{face_beta(Rf[S + x.left], rc), face_beta(rc, Rf[S + x.left + 1]),
+                 face_beta(Rf[S + x.own - kRow], rc), face_beta(rc, Rf[S + x.own + kRow]), zm, zp};
+  };
   auto gs = [&](auto s_tag, auto sa_tag, const Cell& x, const Faces& F, T lo_p, T fv) {
     constexpr int S = decltype(s_tag)::value * kSlot, SA = decltype(sa_tag)::value * kSlot;
     const T D = F.xm + F.xp + F.ym + F.yp + F.zm + F.zp;
@@ -274,12 +286,11 @@ __global__ __launch_bounds__(Shape<T>::TX / 2 * Shape<T>::TY) void k_rbgs_fused2
       const Cell c = tcell[PAR];
       const bool odd = todd[PAR];
       const Faces a2f = ta[PAR], b2f = tb[PAR];   // from step k-2, before this step's A1, B1
-      if (ka >= lo_a1 && ka < n) {
-        ta[PAR] = faces(S3{}, S4{}, c, Rf[S2::value * kSlot + c.own]);
+      ta[PAR] = faces(S3{}, S4{}, c, Rf[S2::value * kSlot + c.own]);
+      if (ka >= lo_a1 && ka < n)
         gs(S3{}, S4{}, c, ta[PAR], Pf[S2::value * kSlot + c.own], odd ? tfw[S3::value].y : tfw[S3::value].x);
-      }
       if (kb >= lo_b1 && kb < n) {
-        tb[PAR] = faces(S2{}, S3{}, c, Rf[S1::value * kSlot + c.own]);
+        tb[PAR] = faces_b1(S2{}, c, a2f.zp, ta[PAR].zm);
         gs(S2{}, S3{}, c, tb[PAR], Pf[S1::value * kSlot + c.own], odd ? tfw[S2::value].y : tfw[S2::value].x);
       }
       if (kA >= lo_a2 && kA < n)
@@ -300,12 +311,13 @@ __global__ __launch_bounds__(Shape<T>::TX / 2 * Shape<T>::TY) void k_rbgs_fused2
       const bool odd = godd[PAR];
       const int d = gd[PAR];
       const Faces a2f = ga[PAR];
-      if (d <= 3 && ka >= lo_a1 && ka < n) {
+      if (d <= 3) {
         ga[PAR] = faces(S3{}, S4{}, c, Rf[S2::value * kSlot + c.own]);
-        gs(S3{}, S4{}, c, ga[PAR], Pf[S2::value * kSlot + c.own], odd ? gfw[S3::value].y : gfw[S3::value].x);
+        if (ka >= lo_a1 && ka < n)
+          gs(S3{}, S4{}, c, ga[PAR], Pf[S2::value * kSlot + c.own], odd ? gfw[S3::value].y : gfw[S3::value].x);
       }
       if (d <= 2 && kb >= lo_b1 && kb < n)
-        gs(S2{}, S3{}, c, faces(S2{}, S3{}, c, Rf[S1::value * kSlot + c.own]), Pf[S1::value * kSlot + c.own],
+        gs(S2{}, S3{}, c, faces_b1(S2{}, c, a2f.zp, ga[PAR].zm), Pf[S1::value * kSlot + c.own],
            odd ? gfw[S2::value].y : gfw[S2::value].x);
       if (d <= 1 && kA >= lo_a2 && kA < n)
         gs(S1{}, S2{}, c, a2f, Pf[S0::value * kSlot + c.own], odd ? gfw[S1::value].y : gfw[S1::value].x);
