@@ -569,6 +569,216 @@ __global__ __launch_bounds__(kMarchThreads) void k_restrict_lds(MarchArgs<T> a) 
   }
 }
 
+// The flexible-CG pass of k_residual_march's FCGX mode on the density form (128 x 8
+// tiles), with the in-plane stencil exchanged through LDS as in k_restrict_lds.  A
+// thread loads d_old, z and rt of its pair's rows and of its share of the halo a plane
+// before they are needed, forms the new direction d = z + beta d_old there, and stages
+// d and rt; after the step's barrier the pair's neighbours come from LDS.  Products,
+// sums, the deferred p += alpha d_old and the per-workgroup partial sums are those of
+// the FCGX mode, in the same order, so the bits are too.
+__global__ __launch_bounds__(kMarchThreads) void k_fcgx_lds(MarchArgs<double> a) {
+  using V2 = double2;
+  using T = double;
+  constexpr int TX = 128, PAIRS = TX / 2, RP = kMarchThreads / PAIRS, TY = 2 * RP;
+  constexpr int LW = TX + 2, LH = TY + 2;
+  __shared__ T Ld[2][LH][LW];
+  __shared__ T Lr[2][LH][LW];
+  const int q = a.q, n = 1 << q;
+  const T inf = __builtin_huge_val();
+  const T zero = T(0);
+  const int tid = threadIdx.x;
+  const int G = gridDim.x, bid = blockIdx.x;
+  const int lid = (G % 8 == 0) ? (bid % 8) * (G / 8) + bid / 8 : bid;   // neighbours on one XCD
+  const int ntx = n / TX, nty = n / TY;
+  const int i0 = (lid % ntx) * TX;
+  const int j0 = ((lid / ntx) % nty) * TY;
+  const int k0 = (lid / (ntx * nty)) * a.kc;
+  const int xt = tid % PAIRS, rp = tid / PAIRS;
+  const int ip = i0 + 2 * xt;
+  const int ja = j0 + 2 * rp, jb = ja + 1;
+  const unsigned oa = off_of<T>(ip, ja, q), ob = off_of<T>(ip, jb, q);
+  const int ra_ = 1 + 2 * rp, rb_ = ra_ + 1, cc = 1 + 2 * xt;
+  const bool first = a.s_zw == nullptr;
+  const double beta = first ? 0.0 : -*a.s_zw / *a.s_dw;
+  auto dn2 = [&](V2 d, V2 z) -> V2 {
+    return first ? z : V2{__builtin_fma(beta, d.x, z.x), __builtin_fma(beta, d.y, z.y)};
+  };
+  auto dn1 = [&](T d, T z) -> T { return first ? z : __builtin_fma(beta, d, z); };
+  auto zload2 = [&](int kk, unsigned off) -> V2 {
+    if (a.zx64) return ld2(plane_rsrc(a.zx64, kk, q), off, 0.0);
+    const float2 zf = ld2(plane_rsrc(a.zx32, kk, q), off >> 1, 0.0f);
+    return V2{static_cast<double>(zf.x), static_cast<double>(zf.y)};
+  };
+  auto zload1 = [&](int kk, unsigned off) -> T {
+    if (a.zx64) return ld1(plane_rsrc(a.zx64, kk, q), off, 0.0);
+    return static_cast<double>(ld1(plane_rsrc(a.zx32, kk, q), off >> 1, 0.0f));
+  };
+  // halo share as in k_restrict_lds
+  int hr = -1, hc = 0;
+  bool hpair = false;
+  unsigned ho = 0;
+  if (tid < 2 * PAIRS) {
+    hpair = true;
+    hr = tid < PAIRS ? 0 : LH - 1;
+    hc = 1 + 2 * (tid % PAIRS);
+    ho = off_of<T>(i0 + 2 * (tid % PAIRS), j0 - 1 + hr, q);
+  } else if (tid < 2 * PAIRS + 2 * TY) {
+    const int e = tid - 2 * PAIRS;
+    hr = 1 + e / 2;
+    hc = (e & 1) ? LW - 1 : 0;
+    ho = off_of<T>((e & 1) ? i0 + TX : i0 - 1, j0 - 1 + hr, q);
+  }
+  // one plane's loads, and the plane as used: the pair's d_old and new direction, rt
+  struct Raw {
+    V2 da, db, za, zb, ra, rb, hd, hz, hrt;
+  };
+  struct Plane {
+    V2 pa, pb, da, db, ra, rb;
+  };
+  auto load = [&](int kk) {
+    const Rsrc dk = plane_rsrc(a.p, kk, q), rk = plane_rsrc(a.rt, kk, q);
+    Raw L;
+    L.da = ld2(dk, oa, zero);
+    L.db = ld2(dk, ob, zero);
+    L.za = zload2(kk, oa);
+    L.zb = zload2(kk, ob);
+    L.ra = ld2(rk, oa, zero);
+    L.rb = ld2(rk, ob, zero);
+    L.hd = V2{zero, zero};
+    L.hz = V2{zero, zero};
+    L.hrt = V2{zero, zero};
+    if (hpair) {
+      L.hd = ld2(dk, ho, zero);
+      L.hz = zload2(kk, ho);
+      L.hrt = ld2(rk, ho, zero);
+    } else if (hr >= 0) {
+      L.hd.x = ld1(dk, ho, zero);
+      L.hz.x = zload1(kk, ho);
+      L.hrt.x = ld1(rk, ho, zero);
+    }
+    return L;
+  };
+  // the new direction of a loaded plane, staged in LDS plane b
+  auto put = [&](int b, const Raw& L) {
+    Plane P;
+    P.pa = dn2(L.da, L.za);
+    P.pb = dn2(L.db, L.zb);
+    P.da = L.da;
+    P.db = L.db;
+    P.ra = L.ra;
+    P.rb = L.rb;
+    Ld[b][ra_][cc] = P.pa.x;
+    Ld[b][ra_][cc + 1] = P.pa.y;
+    Ld[b][rb_][cc] = P.pb.x;
+    Ld[b][rb_][cc + 1] = P.pb.y;
+    Lr[b][ra_][cc] = L.ra.x;
+    Lr[b][ra_][cc + 1] = L.ra.y;
+    Lr[b][rb_][cc] = L.rb.x;
+    Lr[b][rb_][cc + 1] = L.rb.y;
+    if (hpair) {
+      const V2 h = dn2(L.hd, L.hz);
+      Ld[b][hr][hc] = h.x;
+      Ld[b][hr][hc + 1] = h.y;
+      Lr[b][hr][hc] = L.hrt.x;
+      Lr[b][hr][hc + 1] = L.hrt.y;
+    } else if (hr >= 0) {
+      Ld[b][hr][hc] = dn1(L.hd.x, L.hz.x);
+      Lr[b][hr][hc] = L.hrt.x;
+    }
+    return P;
+  };
+
+  // prologue: plane k0 staged; the pair's direction on k0-1 and rt faces to plane k0-1;
+  // plane k0+1 loaded
+  Plane cur = put(k0 & 1, load(k0));
+  const Rsrc d_lo = plane_rsrc(a.p, k0 - 1, q), r_lo = plane_rsrc(a.rt, k0 - 1, q);
+  V2 pa_lo = dn2(ld2(d_lo, oa, zero), zload2(k0 - 1, oa));
+  V2 pb_lo = dn2(ld2(d_lo, ob, zero), zload2(k0 - 1, ob));
+  const V2 la = ld2(r_lo, oa, zero), lb = ld2(r_lo, ob, zero);
+  Raw nxt = load(k0 + 1);
+  const bool in_lo = k0 >= 1;
+  V2 za = in_lo ? V2{face_beta(la.x, cur.ra.x), face_beta(la.y, cur.ra.y)} : V2{zero, zero};
+  V2 zb = in_lo ? V2{face_beta(lb.x, cur.rb.x), face_beta(lb.y, cur.rb.y)} : V2{zero, zero};
+  double acc = 0.0, acc2 = 0.0;
+  for (int k = k0; k < k0 + a.kc; ++k) {
+    __syncthreads();   // plane k staged; the other LDS plane no longer read
+    const Plane hi = put((k + 1) & 1, nxt);
+    nxt = load(k + 2);
+    const int b = k & 1;
+    const V2 pd{Ld[b][ra_ - 1][cc], Ld[b][ra_ - 1][cc + 1]}, pup{Ld[b][rb_ + 1][cc], Ld[b][rb_ + 1][cc + 1]};
+    const T pla = Ld[b][ra_][cc - 1], pra = Ld[b][ra_][cc + 2];
+    const T plb = Ld[b][rb_][cc - 1], prb = Ld[b][rb_][cc + 2];
+    const V2 rd{Lr[b][ra_ - 1][cc], Lr[b][ra_ - 1][cc + 1]}, rup2{Lr[b][rb_ + 1][cc], Lr[b][rb_ + 1][cc + 1]};
+    const T rla = Lr[b][ra_][cc - 1], rra = Lr[b][ra_][cc + 2];
+    const T rlb = Lr[b][rb_][cc - 1], rrb = Lr[b][rb_][cc + 2];
+    const bool in_hi = k + 1 < n;
+    const V2 ha_i{in_hi ? hi.ra.x : inf, in_hi ? hi.ra.y : inf}, hb_i{in_hi ? hi.rb.x : inf, in_hi ? hi.rb.y : inf};
+    const V2 ra = cur.ra, rb = cur.rb;
+    PF<T> Fa, Fb;
+    const T mid0 = face_beta(ra.x, rb.x), mid1 = face_beta(ra.y, rb.y);
+    Fa.x0 = face_beta(rla, ra.x);
+    Fa.x1 = face_beta(ra.x, ra.y);
+    Fa.x2 = face_beta(ra.y, rra);
+    Fa.ym0 = face_beta(rd.x, ra.x);
+    Fa.ym1 = face_beta(rd.y, ra.y);
+    Fa.yp0 = mid0;
+    Fa.yp1 = mid1;
+    Fa.zm0 = za.x;
+    Fa.zm1 = za.y;
+    Fa.zp0 = face_beta(ra.x, ha_i.x);
+    Fa.zp1 = face_beta(ra.y, ha_i.y);
+    Fb.x0 = face_beta(rlb, rb.x);
+    Fb.x1 = face_beta(rb.x, rb.y);
+    Fb.x2 = face_beta(rb.y, rrb);
+    Fb.ym0 = mid0;
+    Fb.ym1 = mid1;
+    Fb.yp0 = face_beta(rb.x, rup2.x);
+    Fb.yp1 = face_beta(rb.y, rup2.y);
+    Fb.zm0 = zb.x;
+    Fb.zm1 = zb.y;
+    Fb.zp0 = face_beta(rb.x, hb_i.x);
+    Fb.zp1 = face_beta(rb.y, hb_i.y);
+    T r0a, r1a, r0b, r1b;
+    const V2 f0{zero, zero};
+    pair_r(Fa, cur.pa, pla, pra, pd, cur.pb, pa_lo, hi.pa, f0, zero, a.inv_h2, r0a, r1a);
+    pair_r(Fb, cur.pb, plb, prb, cur.pa, pup, pb_lo, hi.pb, f0, zero, a.inv_h2, r0b, r1b);
+    const long long plane = static_cast<long long>(k) << (2 * q);
+    const long long ca = plane + oa / sizeof(T), cb = plane + ob / sizeof(T);
+    // the residual of f = 0 is -A d
+    const V2 wa{-r0a, -r1a}, wb{-r0b, -r1b};
+    stream_store(a.w + ca, wa);   // read again only by the update pass
+    stream_store(a.w + cb, wb);
+    // the new direction (read again after the next cycle), and the previous step's
+    // update of p with the old direction
+    stream_store(a.dn + ca, cur.pa);
+    stream_store(a.dn + cb, cur.pb);
+    if (a.pp) {
+      const double alpha = *a.s_alpha;
+      const V2 xa = *reinterpret_cast<const V2*>(a.pp + ca);
+      const V2 xb = *reinterpret_cast<const V2*>(a.pp + cb);
+      stream_store(a.pp + ca, V2{__builtin_fma(alpha, cur.da.x, xa.x), __builtin_fma(alpha, cur.da.y, xa.y)});
+      stream_store(a.pp + cb, V2{__builtin_fma(alpha, cur.db.x, xb.x), __builtin_fma(alpha, cur.db.y, xb.y)});
+    }
+    const V2 rva = ld2(plane_rsrc(a.r, k, q), oa, 0.0), rvb = ld2(plane_rsrc(a.r, k, q), ob, 0.0);
+    acc = fmad(cur.pa.y, wa.y, fmad(cur.pa.x, wa.x, acc));
+    acc = fmad(cur.pb.y, wb.y, fmad(cur.pb.x, wb.x, acc));
+    acc2 = fmad(cur.pa.y, rva.y, fmad(cur.pa.x, rva.x, acc2));
+    acc2 = fmad(cur.pb.y, rvb.y, fmad(cur.pb.x, rvb.x, acc2));
+    pa_lo = cur.pa;
+    pb_lo = cur.pb;
+    za = V2{Fa.zp0, Fa.zp1};
+    zb = V2{Fb.zp0, Fb.zp1};
+    cur = hi;
+  }
+  const double s1 = block_sum(acc);
+  __syncthreads();
+  const double s2 = block_sum(acc2);
+  if (tid == 0) {
+    a.partials[bid] = s1;
+    a.partials2[bid] = s2;
+  }
+}
+
 template <typename T, bool RHO, int MODE>
 hipError_t launch_mode(MarchArgs<T> a, int* nblocks, hipStream_t s) {
   const int n = 1 << a.q;
@@ -722,6 +932,19 @@ hipError_t launch_fcg_x_march(const double* z64, const float* z32, const double*
   a.s_alpha = s_alpha;
   a.dn = dn;
   a.pp = s_zw ? p : nullptr;
+  if (rt && (1 << q) >= 128) {   // the density form: the stencil through LDS
+    const int n = 1 << q;
+    const long long tiles = static_cast<long long>(n / 128) * (n / 8);
+    int kc = 64;
+    while (kc > 2 && tiles * (n / kc) < 1024) kc /= 2;
+    if (kc > n) kc = n;
+    while (tiles * (n / kc) > kNumPartials) kc *= 2;
+    a.kc = kc;
+    const int blocks = static_cast<int>(tiles * (n / kc));
+    *nblocks = blocks;
+    hipLaunchKernelGGL(k_fcgx_lds, dim3(blocks), dim3(kMarchThreads), 0, s, a);
+    return hipGetLastError();
+  }
   return launch_form<kModeFcgX>(a, nblocks, s);
 }
 
