@@ -611,7 +611,7 @@ def coarsening_sweep(args):
     return out
 
 
-TRAFFIC_KERNEL = "k_rbgs_fused2<double, false>"
+TRAFFIC_KERNEL = "k_rbgs_fused2<double, false, false>"
 
 
 def kernel_source_hash():

@@ -144,11 +144,19 @@ bool two_sweep_grid(const mg_ctx* c, int l) {
   return c->view<T>(l).rt != nullptr && mg::fused2_supported(c->lv[l].q);
 }
 
+// zw (FP64 only): the pass also leaves partial sums of pout . zw->w, see ZwSums
+struct ZwSums {
+  const double* w;
+  double* partials;
+  int* nblocks;
+};
+
 template <typename T>
 hipError_t launch_two_sweeps(const mg_ctx* c, int l, const T* pin, T* pout, const T* f, const double* fshift, int order,
-                             bool zero_in) {
+                             bool zero_in, const ZwSums* zw = nullptr) {
   const Level& a = c->lv[l];
-  return mg::launch_rbgs_fused2(pin, pout, f, c->view<T>(l).rt, a.q, a.h, order, fshift, zero_in ? 1 : 0, c->stream);
+  return mg::launch_rbgs_fused2(pin, pout, f, c->view<T>(l).rt, a.q, a.h, order, fshift, zero_in ? 1 : 0, c->stream,
+                                zw ? zw->w : nullptr, zw ? zw->partials : nullptr, zw ? zw->nblocks : nullptr);
 }
 
 template <typename T>
@@ -217,9 +225,11 @@ int first_sweep(mg_ctx* c, T* p, const T* f, const double* fshift, bool zero_in)
   return MG_OK;
 }
 
-// zero_in: p enters as zero (a correction), see smooth(); first_done: see first_sweep()
+// zero_in: p enters as zero (a correction), see smooth(); first_done: see first_sweep();
+// zw: only on a two-sweep grid, where the last pass also sums p . zw->w (flexible CG's z.w)
 template <typename T>
-int vcycle(mg_ctx* c, int l, T* p, const T* f, const double* fshift, bool zero_in = false, bool first_done = false) {
+int vcycle(mg_ctx* c, int l, T* p, const T* f, const double* fshift, bool zero_in = false, bool first_done = false,
+           const ZwSums* zw = nullptr) {
   if (c->lv[l].n <= mg::kCoarseCycleMaxN) {
     // grids of 16^3 and below: the rest of the cycle in one single-workgroup launch
     mg::CoarseCycle<T> a{};
@@ -251,9 +261,10 @@ int vcycle(mg_ctx* c, int l, T* p, const T* f, const double* fshift, bool zero_i
     MG_TRY(residual_restrict<T>(c, l, t, f, fshift, next.f, next.e));
     MG_TRY(vcycle<T>(c, l + 1, next.e, next.f, nullptr, true));
     MG_HIP(mg::launch_prolong_add<T>(next.e, t, c->lv[l].mask, c->lv[l].q, c->stream));
-    MG_HIP(launch_two_sweeps<T>(c, l, t, p, f, fshift, MG_POST, false));
+    MG_HIP(launch_two_sweeps<T>(c, l, t, p, f, fshift, MG_POST, false, zw));
     return MG_OK;
   }
+  if (zw) return fail(MG_EINVAL, "z.w sums asked of a grid that does not sweep two to a pass");
   MG_TRY(smooth<T>(c, l, p, f, fshift, 2, MG_PRE, zero_in, first_done));
   MG_TRY(residual_restrict<T>(c, l, p, f, fshift, next.f, next.e));
   MG_TRY(vcycle<T>(c, l + 1, next.e, next.f, nullptr, true));   // restriction zeroed next.e
@@ -387,6 +398,8 @@ int solve_one(mg_ctx* c, const double* f, double* p, double tol, int max_cycles,
       if (mixed) return vcycle<float>(c, 0, e32, r32, nullptr, true, first_done);
       return vcycle<double>(c, 0, kz, kr, nullptr, true, first_done);
     };
+    // FP64 preconditioning on a two-sweep finest grid: z.w comes out of its last pass
+    const bool zw_fused = !mixed && two_sweep_grid<double>(c, 0) && a.n > mg::kCoarseCycleMaxN;
     auto precondition_first_sweep = [&]() -> int {
       if (mixed) return first_sweep<float>(c, e32, r32, nullptr, true);
       return first_sweep<double>(c, kz, kr, nullptr, true);
@@ -442,8 +455,13 @@ int solve_one(mg_ctx* c, const double* f, double* p, double tol, int max_cycles,
                         sn[S_DW]);
         break;
       }
-      MG_TRY(precondition(ahead));
-      MG_HIP(mg::launch_fcg_zw(z64, z32, kw, q, part(c, 3), &nb, c->stream));
+      if (zw_fused) {   // z.w from the preconditioner's last pass
+        const ZwSums zw{kw, part(c, 3), &nb};
+        MG_TRY(vcycle<double>(c, 0, kz, kr, nullptr, true, ahead, &zw));
+      } else {
+        MG_TRY(precondition(ahead));
+        MG_HIP(mg::launch_fcg_zw(z64, z32, kw, q, part(c, 3), &nb, c->stream));
+      }
       MG_TRY(reduce_set(c, 3, nb, S_ZW));
       MG_TRY(direction(false));
     }

@@ -39,6 +39,7 @@
 
 #include "mg_buffer.h"
 #include "mg_kernels.h"
+#include "mg_plan.h"
 
 namespace mg {
 
@@ -77,10 +78,12 @@ __device__ __forceinline__ int ring_of(int r, int c) {
 __device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
-template <typename T, bool ZIN>
+// ZW (FP64, post-smoothing of a flexible-CG preconditioner): also the workgroup's sum of
+// pout * w over its tile, the planes in order, into partials[blockIdx.x].
+template <typename T, bool ZIN, bool ZW>
 __global__ __launch_bounds__(Shape<T>::TX / 2 * Shape<T>::TY) void k_rbgs_fused2(
     const T* __restrict__ pin, T* __restrict__ pout, const T* __restrict__ f, const T* __restrict__ rt, int q, int kc,
-    T h2, int first, const double* __restrict__ fshift) {
+    T h2, int first, const double* __restrict__ fshift, const double* __restrict__ w, double* __restrict__ partials) {
   using V2 = typename buf::Vec2<T>::type;
   constexpr int kTX = Shape<T>::TX, kTY = Shape<T>::TY;
   constexpr int kNT = kTX / 2 * kTY;          // one thread per tile x-pair
@@ -250,6 +253,7 @@ __global__ __launch_bounds__(Shape<T>::TX / 2 * Shape<T>::TY) void k_rbgs_fused2
   // on plane k, and the faces of the A1 and B1 updates for A2 and B2 two steps on
   // (tile), and of the ring's A1 for its A2
   T below_p[2] = {T(0), T(0)};
+  double zw = 0.0;   // ZW: this thread's sum of pout * w
   Faces ta[2], tb[2], ga[2];
 
   // ---- prologue: planes ks .. ks+3 staged (slots 0..3), ks+4 in registers, f of ks .. ks+3
@@ -280,6 +284,8 @@ __global__ __launch_bounds__(Shape<T>::TX / 2 * Shape<T>::TY) void k_rbgs_fused2
     store(k + 4, S4{});
     fetch(k + 5);
     load_f(k + 4, tfw[S4::value], gfw[S4::value]);
+    V2 wk{T(0), T(0)};   // ZW: w of the tile pair on plane k, read while the step runs
+    if constexpr (ZW) wk = ld2(plane_rsrc(w, k, q), tf_off, 0.0);
     __syncthreads();
     const int ka = k + 3, kb = k + 2, kA = k + 1;
     {
@@ -301,6 +307,7 @@ __global__ __launch_bounds__(Shape<T>::TX / 2 * Shape<T>::TY) void k_rbgs_fused2
         const T v0 = Pf[S0::value * kSlot + out_off], v1 = Pf[S0::value * kSlot + out_off + kWP];
         *reinterpret_cast<V2*>(reinterpret_cast<char*>(pout + (static_cast<long long>(k) << (2 * q))) + tf_off) =
             V2{v0, v1};
+        if constexpr (ZW) zw = __builtin_fma(v1, wk.y, __builtin_fma(v0, wk.x, zw));
       }
       // this column's cell on plane k+1 is used by B2 on plane k+2, two steps on
       below_p[PAR] = Pf[S1::value * kSlot + c.own];
@@ -336,6 +343,18 @@ __global__ __launch_bounds__(Shape<T>::TX / 2 * Shape<T>::TY) void k_rbgs_fused2
       step(k + 5, integral_constant<int, 5>{});
     }
   }
+  if constexpr (ZW) {   // the workgroup's sum: waves in order, through the first LDS words
+    for (int off = 32; off > 0; off >>= 1) zw += __shfl_xor(zw, off, 64);
+    __syncthreads();   // every wave is past its last read of the staged planes
+    double* red = reinterpret_cast<double*>(Pf);
+    if ((tid & 63) == 0) red[tid >> 6] = zw;
+    __syncthreads();
+    if (tid == 0) {
+      double s = 0.0;
+      for (int v = 0; v < kNT / 64; ++v) s += red[v];
+      partials[blockIdx.x] = s;
+    }
+  }
 }
 
 }  // namespace
@@ -344,28 +363,40 @@ int fused2_supported(int q) { return (1 << q) >= 256; }
 
 template <typename T>
 hipError_t launch_rbgs_fused2(const T* pin, T* pout, const T* f, const T* rt, int q, double h, int order,
-                              const double* fshift, int zero_in, hipStream_t s) {
+                              const double* fshift, int zero_in, hipStream_t s, const double* w, double* partials,
+                              int* nblocks) {
   constexpr int TX = Shape<T>::TX, TY = Shape<T>::TY;
   const int n = 1 << q;
   if (!fused2_supported(q) || !rt || pin == pout) return hipErrorInvalidValue;
+  const bool zw = w != nullptr;
+  if (zw && (sizeof(T) != 8 || zero_in || !partials || !nblocks)) return hipErrorInvalidValue;
   const long long tiles = static_cast<long long>(n / TX) * (n / TY);
   // z-chunks as long as possible while every compute unit still gets a workgroup
   int kc = n;
   while (kc > 8 && tiles * (n / kc) < 256) kc /= 2;
   const long long blocks = tiles * (n / kc);
+  if (zw && blocks > kNumPartials) return hipErrorInvalidValue;
   const T h2 = static_cast<T>(h * h);
   const int first = order == 0 ? 0 : 1;   // pre-smoothing: red first; post-smoothing: black first
   const dim3 grid(static_cast<unsigned>(blocks)), block(TX / 2 * TY);
-  if (zero_in)
-    hipLaunchKernelGGL((k_rbgs_fused2<T, true>), grid, block, 0, s, pin, pout, f, rt, q, kc, h2, first, fshift);
-  else
-    hipLaunchKernelGGL((k_rbgs_fused2<T, false>), grid, block, 0, s, pin, pout, f, rt, q, kc, h2, first, fshift);
+  if (zw) {
+    if constexpr (sizeof(T) == 8)
+      hipLaunchKernelGGL((k_rbgs_fused2<T, false, true>), grid, block, 0, s, pin, pout, f, rt, q, kc, h2, first,
+                         fshift, w, partials);
+    *nblocks = static_cast<int>(blocks);
+  } else if (zero_in) {
+    hipLaunchKernelGGL((k_rbgs_fused2<T, true, false>), grid, block, 0, s, pin, pout, f, rt, q, kc, h2, first, fshift,
+                       nullptr, nullptr);
+  } else {
+    hipLaunchKernelGGL((k_rbgs_fused2<T, false, false>), grid, block, 0, s, pin, pout, f, rt, q, kc, h2, first,
+                       fshift, nullptr, nullptr);
+  }
   return hipGetLastError();
 }
 
 template hipError_t launch_rbgs_fused2<float>(const float*, float*, const float*, const float*, int, double, int,
-                                              const double*, int, hipStream_t);
+                                              const double*, int, hipStream_t, const double*, double*, int*);
 template hipError_t launch_rbgs_fused2<double>(const double*, double*, const double*, const double*, int, double, int,
-                                               const double*, int, hipStream_t);
+                                               const double*, int, hipStream_t, const double*, double*, int*);
 
 }  // namespace mg

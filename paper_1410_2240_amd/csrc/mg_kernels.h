@@ -108,11 +108,14 @@ hipError_t launch_rbgs_half(T* p, const T* f, const T* bx, const T* by, const T*
 // the input is known to be zero (a correction's first sweep), so pin is not read.
 int fused_sweep_supported(int q);
 // Two red-black sweeps in one pass (density form, grids of 256^3 and up): pin -> pout
-// (distinct), order as launch_rbgs_fused; bit for bit two one-pass sweeps.
+// (distinct), order as launch_rbgs_fused; bit for bit two one-pass sweeps.  With w
+// (FP64, not zero_in): also one partial sum of pout * w per workgroup into partials,
+// their number into *nblocks (at most kNumPartials).
 int fused2_supported(int q);
 template <typename T>
 hipError_t launch_rbgs_fused2(const T* pin, T* pout, const T* f, const T* rt, int q, double h, int order,
-                              const double* fshift, int zero_in, hipStream_t s);
+                              const double* fshift, int zero_in, hipStream_t s, const double* w = nullptr,
+                              double* partials = nullptr, int* nblocks = nullptr);
 template <typename T>
 hipError_t launch_rbgs_fused(const T* pin, T* pout, const T* f, const T* bx, const T* by, const T* bz, const T* rt,
                              int q, double h, int order, const double* fshift, int zero_in, hipStream_t s);

@@ -84,6 +84,24 @@ def test_fcg_bitwise():
     assert torch.equal(pa, pb)
 
 
+def test_fcg_256_fused_zw_follows_the_separate_pass():
+    """On a 256^3 grid set up from rho, the FP64 preconditioning cycle ends in the
+    two-sweep pass, which also sums flexible CG's z.w as it writes z; set up from face
+    arrays, the grid sweeps once per pass and z.w has a pass of its own.  All else is
+    bit for bit the same, so the two solves differ only in the order of that sum's
+    terms: histories equal to rounding, the same solution."""
+    inp, a, b = pair(256, krylov=True)
+    print("density-form FCG 256: fused z.w against its own pass", flush=True)
+    f = dev(inp.f)
+    pa, ha, sa = a.solve(f, tol=1e-10, max_cycles=60)
+    pb, hb, sb = b.solve(f, tol=1e-10, max_cycles=60)
+    assert sa["status"] == 0 and sb["status"] == 0
+    assert ha[0] == hb[0] and abs(len(ha) - len(hb)) <= 1
+    for x, y in list(zip(ha, hb))[:10]:
+        assert abs(x - y) <= 1e-9 * y, (ha[:10], hb[:10])
+    assert relerr(host(pa), host(pb)) <= 1e-9
+
+
 @pytest.mark.parametrize("krylov", [False, True])
 def test_mixed_density_form_converges_to_the_same_solution(krylov):
     """FP32 cycles form their finest coefficients from an FP32 density copy (not bitwise
