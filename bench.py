@@ -509,11 +509,12 @@ def rk2_leg(N, args):
 
 
 def level_breakdown(args):
-    """Where a V(2,2) cycle spends its time on the bench field: per grid with a coarser
-    one below it (down to 32^3), the four sweeps, the residual + restriction and the
-    prolongation, each timed through the component entry points with HIP events (best
-    of the mean of 20 calls); the single-workgroup tail (16^3 and below) is the whole
-    cycle minus those.  FP64 cycle, and the FP32 cycle of a mixed context."""
+    """Where a V(2,2) cycle spends its time on the bench field: per grid of 128^3 and up,
+    the four sweeps, the residual + restriction and the prolongation, each timed through
+    the component entry points with HIP events (best of the mean of 20 calls); the grids
+    of 64^3 and below (four block-sweep launches each, the restriction and prolongation
+    fused into them, then the single-workgroup tail from 16^3 down) are the whole cycle
+    minus those.  FP64 cycle, and the FP32 cycle of a mixed context."""
     import torch
     import fields
     from paper_1410_2240_amd import MG
@@ -545,7 +546,7 @@ def level_breakdown(args):
         grids, above = [], 0.0
         for lv in range(mg.levels - 1):
             n_l, _ = mg.level_info(lv)
-            if n_l <= 16:
+            if n_l <= 64:
                 break
             p = torch.zeros((n_l,) * 3, dtype=dt, device="cuda")
             f = f0.to(dt) if lv == 0 else torch.randn((n_l,) * 3, dtype=torch.float64, device="cuda",
@@ -561,7 +562,7 @@ def level_breakdown(args):
         pf = torch.zeros_like(f0, dtype=dt)
         ff = f0.to(dt)
         cycle = tm(lambda: mg.vcycle(pf, ff))
-        out[prec] = {"cycle_us": cycle, "grids": grids, "tail_us": cycle - above}
+        out[prec] = {"cycle_us": cycle, "grids": grids, "grids_64_and_below_us": cycle - above}
         log(f"level breakdown {prec}: {out[prec]}")
         del mg, pf, ff
         torch.cuda.empty_cache()

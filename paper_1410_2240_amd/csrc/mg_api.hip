@@ -131,9 +131,10 @@ long long cells(const Level& a) { return static_cast<long long>(a.n) * a.n * a.n
 
 // ---------------------------------------------------------------- V-cycle (T = double/float)
 
-// `sweeps` red-black sweeps of A p = f on level l.  Large grids use the one-pass fused
-// sweep, which alternates p with the level's second buffer; an odd count ends with a
-// copy back.  Small grids use two in-place half-sweeps per sweep.  zero_in: p is known to
+// `sweeps` red-black sweeps of A p = f on level l.  Grids of 64^3 and up use the one-pass
+// fused sweep (32^3 and 64^3 grids with face arrays the block-per-workgroup sweep), which
+// alternates p with the level's second buffer; an odd count ends with a copy back.
+// Smaller grids use two in-place half-sweeps per sweep.  zero_in: p is known to
 // be zero, so the first one-pass sweep does not read it (p's memory may then hold
 // anything; half-sweep grids still need it zeroed).  first_done: the first sweep
 // (p -> second buffer) has already been queued (see first_sweep), so start from its output.
@@ -164,7 +165,8 @@ int smooth(mg_ctx* c, int l, T* p, const T* f, const double* fshift, int sweeps,
            bool first_done = false) {
   const Level& a = c->lv[l];
   const View<T> v = c->view<T>(l);
-  if (mg::fused_sweep_supported(a.q)) {
+  const bool box = !v.rt && mg::box_sweep_supported(a.q);   // 32^3 and 64^3 from face arrays
+  if (mg::fused_sweep_supported(a.q) || box) {
     T* src = first_done ? v.t : p;
     T* dst = first_done ? p : v.t;
     const bool two = two_sweep_grid<T>(c, l);
@@ -178,8 +180,12 @@ int smooth(mg_ctx* c, int l, T* p, const T* f, const double* fshift, int sweeps,
       }
     }
     for (; s < sweeps; ++s) {
-      MG_HIP(mg::launch_rbgs_fused<T>(src, dst, f, v.bx, v.by, v.bz, v.rt, a.q, a.h, order, fshift,
-                                      zero_in && s == 0, c->stream));
+      if (box)
+        MG_HIP(mg::launch_rbgs_box<T>(src, dst, f, v.bx, v.by, v.bz, a.q, a.h, order, fshift, zero_in && s == 0,
+                                      c->stream));
+      else
+        MG_HIP(mg::launch_rbgs_fused<T>(src, dst, f, v.bx, v.by, v.bz, v.rt, a.q, a.h, order, fshift,
+                                        zero_in && s == 0, c->stream));
       T* tmp = src;
       src = dst;
       dst = tmp;
@@ -265,6 +271,22 @@ int vcycle(mg_ctx* c, int l, T* p, const T* f, const double* fshift, bool zero_i
     return MG_OK;
   }
   if (zw) return fail(MG_EINVAL, "z.w sums asked of a grid that does not sweep two to a pass");
+  const Level& a = c->lv[l];
+  const View<T> v = c->view<T>(l);
+  if (!v.rt && mg::box_sweep_supported(a.q)) {
+    // 32^3 and 64^3 from face arrays, four launches: pre-smoothing p -> t -> p, the second
+    // sweep also restricting its residual; post-smoothing from p plus the prolongated
+    // correction -> t -> p
+    if (!first_done)
+      MG_HIP(mg::launch_rbgs_box<T>(p, v.t, f, v.bx, v.by, v.bz, a.q, a.h, MG_PRE, fshift, zero_in, c->stream));
+    MG_HIP(mg::launch_rbgs_box_restrict<T>(v.t, p, f, v.bx, v.by, v.bz, a.q, a.h, MG_PRE, fshift, next.f, next.e,
+                                           c->stream));
+    MG_TRY(vcycle<T>(c, l + 1, next.e, next.f, nullptr, true));
+    MG_HIP(mg::launch_rbgs_box_prolong<T>(p, v.t, f, v.bx, v.by, v.bz, a.q, a.h, MG_POST, fshift, next.e, a.mask,
+                                          c->stream));
+    MG_HIP(mg::launch_rbgs_box<T>(v.t, p, f, v.bx, v.by, v.bz, a.q, a.h, MG_POST, fshift, 0, c->stream));
+    return MG_OK;
+  }
   MG_TRY(smooth<T>(c, l, p, f, fshift, 2, MG_PRE, zero_in, first_done));
   MG_TRY(residual_restrict<T>(c, l, p, f, fshift, next.f, next.e));
   MG_TRY(vcycle<T>(c, l + 1, next.e, next.f, nullptr, true));   // restriction zeroed next.e

@@ -107,6 +107,24 @@ hipError_t launch_rbgs_half(T* p, const T* f, const T* bx, const T* by, const T*
 // rt != nullptr: coefficients from the density form instead of bx, by, bz.  zero_in:
 // the input is known to be zero (a correction's first sweep), so pin is not read.
 int fused_sweep_supported(int q);
+// One red-black sweep of a 32^3 or 64^3 grid (face arrays) in one launch, a block of
+// cells per workgroup: pin -> pout (distinct), order and zero_in as launch_rbgs_fused,
+// whose bits it gives.
+int box_sweep_supported(int q);
+template <typename T>
+hipError_t launch_rbgs_box(const T* pin, T* pout, const T* f, const T* bx, const T* by, const T* bz, int q, double h,
+                           int order, const double* fshift, int zero_in, hipStream_t s);
+// The same sweep, then the residual of its output restricted as launch_residual_restrict
+// does (fc, ec = 0 on the grid below), bit for bit.
+template <typename T>
+hipError_t launch_rbgs_box_restrict(const T* pin, T* pout, const T* f, const T* bx, const T* by, const T* bz, int q,
+                                    double h, int order, const double* fshift, T* fc, T* ec, hipStream_t s);
+// The same sweep of pin + mask * prolong(ec), bit for bit launch_prolong_add(ec, pin)
+// followed by launch_rbgs_box; pin itself is not changed.
+template <typename T>
+hipError_t launch_rbgs_box_prolong(const T* pin, T* pout, const T* f, const T* bx, const T* by, const T* bz, int q,
+                                   double h, int order, const double* fshift, const T* ec, const uint8_t* mask,
+                                   hipStream_t s);
 // Two red-black sweeps in one pass (density form, grids of 256^3 and up): pin -> pout
 // (distinct), order as launch_rbgs_fused; bit for bit two one-pass sweeps.  With w
 // (FP64, not zero_in): also one partial sum of pout * w per workgroup into partials,

@@ -468,7 +468,8 @@ __global__ __launch_bounds__(kBlock) void k_residual_restrict(const T* __restric
 // p += mask * trilinear(ec); 1-D weights 3/4 (parent) and 1/4 (nearer neighbour),
 // periodic in x and y, parent reused for a z neighbour outside the grid.  One thread
 // per coarse cell updates its 8 children (x-pairs on two rows of two planes), applying
-// the 1-D weights in x, then y, then z.
+// the 1-D weights in x, then y, then z, each as one fused multiply-add (3/4 a + (1/4 b),
+// the second product exact), so that the rounding is fixed by the source.
 template <typename T>
 __device__ __forceinline__ void prolong_cell(const T* __restrict__ ec, T* __restrict__ p,
                                              const uint8_t* __restrict__ mask, int q, int C) {
@@ -487,8 +488,8 @@ __device__ __forceinline__ void prolong_cell(const T* __restrict__ ec, T* __rest
     for (int a = 0; a < 3; ++a) {
       const int row = cell(0, Jy[a], Kz[b], qc);
       const T e0 = ec[row + Ix[0]], e1 = ec[row + Ix[1]], e2 = ec[row + Ix[2]];
-      ax[b][a][0] = w3 * e1 + w1 * e0;
-      ax[b][a][1] = w3 * e1 + w1 * e2;
+      ax[b][a][0] = fmad(w3, e1, w1 * e0);
+      ax[b][a][1] = fmad(w3, e1, w1 * e2);
     }
 #pragma unroll
   for (int dz = 0; dz < 2; ++dz)
@@ -503,9 +504,9 @@ __device__ __forceinline__ void prolong_cell(const T* __restrict__ ec, T* __rest
 #pragma unroll
       for (int dx = 0; dx < 2; ++dx) {
         const int ay = dy ? 2 : 0, bz_ = dz ? 2 : 0;   // nearer neighbour row / plane
-        const T lo = w3 * ax[1][1][dx] + w1 * ax[1][ay][dx];
-        const T hi = w3 * ax[bz_][1][dx] + w1 * ax[bz_][ay][dx];
-        out[dx] = w3 * lo + w1 * hi;
+        const T lo = fmad(w3, ax[1][1][dx], w1 * ax[1][ay][dx]);
+        const T hi = fmad(w3, ax[bz_][1][dx], w1 * ax[bz_][ay][dx]);
+        out[dx] = fmad(w3, lo, w1 * hi);
       }
       if (mk.x) v.x += out[0];
       if (mk.y) v.y += out[1];
@@ -623,11 +624,12 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle(CoarseCycle<T> 
     f[0][c] = a.f[0][c];
   }
   __syncthreads();
-  // FP32: the face coefficients of the cells this thread updates on the two grids that
-  // are smoothed, loaded once: every half-sweep would otherwise wait for them from L2
-  // again, one pair after another.  Pair slot u of grid l is pair tid + u x 512 (at most
-  // 4 on a 16^3 grid), colour 0 / 1 its red / black cell.  (FP64 reads them from L2 in
-  // each half-sweep: held in registers they would spill.)
+  // The face coefficients of the cells this thread updates on the grids that are
+  // smoothed, loaded once (every half-sweep would otherwise wait for them from L2 again):
+  // on the first grid in FP32, on the second in both precisions.  Pair slot u of grid l
+  // is pair tid + u x 512 (at most 4 on a 16^3 grid), colour 0 / 1 its red / black cell.
+  // FP64 reads the first grid's from L2 in each half-sweep, all of a thread's pairs at
+  // once: held in registers they would spill.
   constexpr bool PRE = sizeof(T) == 4;
   constexpr int U0 = (kCoarseCycleMaxN * kCoarseCycleMaxN * kCoarseCycleMaxN / 2) / kCoarseThreads;
   struct CF {
@@ -659,7 +661,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle(CoarseCycle<T> 
     }
   };
   preload0();
-  if (PRE && last > 1 && tid < (1 << (3 * a.q[1] - 1))) {
+  if (last > 1 && tid < (1 << (3 * a.q[1] - 1))) {   // the second grid's: both precisions
     cf1[0] = load_cf(1, tid, 0);
     cf1[1] = load_cf(1, tid, 1);
   }
@@ -682,17 +684,22 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle(CoarseCycle<T> 
   };
   auto sweep = [&](int l, int colour, const T* bx, const T* by, const T* bz) {
     const T fs = (l == 0 && a.fshift) ? static_cast<T>(*a.fshift) : T(0);
-    if constexpr (!PRE) {
-      for (int pr = tid; pr < (1 << (3 * a.q[l] - 1)); pr += kCoarseThreads)
-        gs_pair(e[l], f[l], bx, by, bz, a.q[l], a.h2[l], colour, fs, pr);
-    } else if (l == 0) {
+    if (l == 1) {
+      if (tid < (1 << (3 * a.q[1] - 1))) gs_pre(1, tid, colour, cf1[colour], fs);
+    } else if constexpr (!PRE) {
+      // a fixed trip count, unrolled, so that the coefficient loads of all of a thread's
+      // pairs are in flight together
+#pragma unroll
+      for (int u = 0; u < U0; ++u) {
+        const int pr = tid + u * kCoarseThreads;
+        if (pr < (1 << (3 * a.q[0] - 1))) gs_pair(e[0], f[0], bx, by, bz, a.q[0], a.h2[0], colour, fs, pr);
+      }
+    } else {
 #pragma unroll
       for (int u = 0; u < U0; ++u) {
         const int pr = tid + u * kCoarseThreads;
         if (pr < (1 << (3 * a.q[0] - 1))) gs_pre(0, pr, colour, cf0[u][colour], fs);
       }
-    } else if (tid < (1 << (3 * a.q[1] - 1))) {
-      gs_pre(1, tid, colour, cf1[colour], fs);
     }
     __syncthreads();
   };

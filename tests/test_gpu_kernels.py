@@ -201,8 +201,9 @@ def problem128():
 @pytest.mark.parametrize("order", [0, 1])
 @pytest.mark.parametrize("sweeps", [1, 2])
 def test_fused_sweep_fp64(problem128, level, order, sweeps):
-    """Grids of 64^3 and up run one red-black sweep per pass (tiles, z-chunks, halos):
-    the result must equal the two half-sweeps of the oracle."""
+    """Grids of 64^3 and up run one red-black sweep per pass (128^3: tiles, z-chunks,
+    halos; the 64^3 grid below it, from face arrays: 8^3 blocks with a 2-cell halo, one
+    workgroup each): the result must equal the two half-sweeps of the oracle."""
     N, H, mg = problem128
     lev = H.levels[level]
     g = np.random.default_rng(100 + level)
@@ -211,6 +212,25 @@ def test_fused_sweep_fp64(problem128, level, order, sweeps):
     want = omg.smooth(p, f, lev, sweeps, (omg.RED, omg.BLACK) if order == 0 else (omg.BLACK, omg.RED))
     got = host(mg.smooth(level, dev(p), dev(f), sweeps, order))
     assert maxrel(got, want) <= TOL64
+
+
+def test_block_sweep_vcycle_64_matches_oracle(problem128):
+    """A V-cycle from the 64^3 grid of the 128^3 hierarchy down: on the 64^3 and 32^3
+    grids the block sweeps, the second pre-smoothing sweep also restricting its
+    residual and the first post-smoothing sweep adding the prolongated correction
+    first; against the oracle's cycle on the same grids."""
+    from oracle.multigrid import Hierarchy
+    from paper_1410_2240_amd import MG
+    N, H, _ = problem128
+    lev = H.levels[1]
+    sub = Hierarchy(levels=H.levels[1:], coarse_pinv=H.coarse_pinv)
+    mg = MG(dev(lev.bx), dev(lev.by), dev(lev.bz), dev(lev.mask.astype(np.uint8)), h=lev.h)
+    g = np.random.default_rng(120)
+    p = np.where(lev.mask, g.standard_normal(lev.bx.shape), 0.0)
+    f = project(g.standard_normal(lev.bx.shape), lev.mask)
+    want = omg.vcycle(sub, p, f)
+    got = host(mg.vcycle(dev(p), dev(f)))
+    assert maxrel(got, want) <= 1e-11
 
 
 @pytest.mark.parametrize("order", [0, 1])
