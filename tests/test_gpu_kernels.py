@@ -233,15 +233,18 @@ def test_block_sweep_vcycle_64_matches_oracle(problem128):
     assert maxrel(got, want) <= 1e-11
 
 
+@pytest.mark.parametrize("level", [0, 1])
 @pytest.mark.parametrize("order", [0, 1])
-def test_fused_sweep_fp32(problem128, order):
+def test_fused_sweep_fp32(problem128, level, order):
+    """FP32 sweeps of the 128^3 grid (one-pass, z-marching) and of the 64^3 grid below it
+    (block sweeps) against the oracle in float32."""
     N, H, mg = problem128
-    lev32 = omg.fp32_levels(H)[0]
-    g = np.random.default_rng(110)
+    lev32 = omg.fp32_levels(H)[level]
+    g = np.random.default_rng(110 + level)
     p = f32(np.where(lev32.mask, g.standard_normal(lev32.bx.shape), 0.0))
     f = f32(project(g.standard_normal(lev32.bx.shape), lev32.mask))
     want = omg.smooth(p, f, lev32, 2, (omg.RED, omg.BLACK) if order == 0 else (omg.BLACK, omg.RED))
-    got = host(mg.smooth(0, dev(p), dev(f), 2, order))
+    got = host(mg.smooth(level, dev(p), dev(f), 2, order))
     assert maxrel(got, want) <= TOL32
 
 
