@@ -12,6 +12,15 @@
 // (p_in -> p_out), since workgroups read halo cells that others write.  The update is
 // that of the one-pass z-marching sweep (the same fused multiply-adds in the same order
 // and the same quotient), so both give the same bits.
+//
+// Two variants take the launches around a V-cycle's coarse correction (section 3.1's
+// cycle: smooth, restrict the residual, correct from the grid below, smooth).  The
+// restricting one is the second pre-smoothing sweep: with a 3-cell halo it also updates
+// the second colour on a 1-cell ring, so the block's residual can be formed from final
+// values, and it writes the mean of each 2^3 child set to the grid below.  The
+// prolongating one is the first post-smoothing sweep: while staging p it adds the
+// trilinear interpolation of the coarse correction on active cells.  Both give the bits
+// of the separate residual-restriction and prolongation passes.
 #include "mg_buffer.h"
 #include "mg_kernels.h"
 
