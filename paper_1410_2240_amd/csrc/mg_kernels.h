@@ -44,13 +44,19 @@ __device__ __forceinline__ float face_beta(float a, float b) {
 }
 
 // The quotient of a Gauss-Seidel update, numerator over the diagonal D > 0 (a sum of at
-// most six face products, far from the ends of the range).  FP64: the correctly rounded
-// quotient.  FP32 (the cycles of a mixed-precision solve, whose result only corrects an
-// FP64 iterate): the reciprocal of D, the product, and one correction from the exact
-// remainder n - D q, within an ulp of the rounded quotient in four instructions where the
-// IEEE division takes about ten.  Every FP32 sweep on the one-pass and two-sweep paths
-// uses it, so they stay bit for bit the same.
-__device__ __forceinline__ double gs_quotient(double n, double d) { return n / d; }
+// most six face products, far from the ends of the range): the reciprocal of D, the
+// product, and one correction from the exact remainder n - D q (Markstein's scheme).
+// With the reciprocal itself refined by a Newton step (FP64; FP32 takes the hardware
+// reciprocal as it is, since its result only corrects an FP64 iterate), the quotient is
+// within an ulp of the rounded one and in practice is the rounded one, in fewer
+// instructions than the IEEE division and with a shorter dependency chain.  Every sweep
+// calls it, so the one-pass, two-sweep, block and half-sweep paths give the same bits.
+__device__ __forceinline__ double gs_quotient(double n, double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = __builtin_fma(r, __builtin_fma(-d, r, 1.0), r);
+  const double q = n * r;
+  return __builtin_fma(__builtin_fma(-d, q, n), r, q);
+}
 __device__ __forceinline__ float gs_quotient(float n, float d) {
   const float r = __builtin_amdgcn_rcpf(d);
   const float q = n * r;

@@ -422,7 +422,7 @@ __device__ __forceinline__ void gs_pair(T* __restrict__ p, const T* __restrict__
   const T D = diag(F);
   if (!(D > T(0))) return;
   const T S = F.xm * pxm + F.xp * pxp + F.ym * pym + F.yp * pyp + F.zm * pzm + F.zp * pzp;
-  p[c] = (S - h2 * (fc - fs)) / D;
+  p[c] = gs_quotient(S - h2 * (fc - fs), D);
 }
 
 template <typename T>
@@ -680,7 +680,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle(CoarseCycle<T> 
     const T D = C.xm + C.xp + C.ym + C.yp + C.zm + C.zp;
     if (!(D > T(0))) return;
     const T S = C.xm * pxm + C.xp * pxp + C.ym * pym + C.yp * pyp + C.zm * pzm + C.zp * pzp;
-    p[c] = (S - a.h2[l] * (fc - fs)) / D;
+    p[c] = gs_quotient(S - a.h2[l] * (fc - fs), D);
   };
   auto sweep = [&](int l, int colour, const T* bx, const T* by, const T* bz) {
     const T fs = (l == 0 && a.fshift) ? static_cast<T>(*a.fshift) : T(0);
