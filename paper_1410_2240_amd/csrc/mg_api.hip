@@ -92,6 +92,7 @@ struct mg_ctx {
   double* scal = nullptr;
   long long* counters = nullptr;
   double *kr = nullptr, *kz = nullptr, *kd = nullptr, *kd2 = nullptr, *kw = nullptr;   // flexible-CG vectors
+  double* kr2 = nullptr;   // a second residual (absent unless the plan holds one)
   double* host = nullptr;   // pinned, S_COUNT doubles
   hipEvent_t read_done = nullptr;   // the last read-back of scalars has landed in host
   long long active = 0, dropped = 0;
@@ -145,10 +146,10 @@ bool two_sweep_grid(const mg_ctx* c, int l) {
   return c->view<T>(l).rt != nullptr && mg::fused2_supported(c->lv[l].q);
 }
 
-// zw (FP64 only): the pass also leaves partial sums of pout . zw->w, see ZwSums
+// What an FP64 two-sweep pass of flexible CG also does (launch_rbgs_fused2), and where
+// the number of its partial sums goes.
 struct ZwSums {
-  const double* w;
-  double* partials;
+  mg::Fused2Extra x;
   int* nblocks;
 };
 
@@ -157,7 +158,7 @@ hipError_t launch_two_sweeps(const mg_ctx* c, int l, const T* pin, T* pout, cons
                              bool zero_in, const ZwSums* zw = nullptr) {
   const Level& a = c->lv[l];
   return mg::launch_rbgs_fused2(pin, pout, f, c->view<T>(l).rt, a.q, a.h, order, fshift, zero_in ? 1 : 0, c->stream,
-                                zw ? zw->w : nullptr, zw ? zw->partials : nullptr, zw ? zw->nblocks : nullptr);
+                                zw ? &zw->x : nullptr, zw ? zw->nblocks : nullptr);
 }
 
 template <typename T>
@@ -420,8 +421,11 @@ int solve_one(mg_ctx* c, const double* f, double* p, double tol, int max_cycles,
       if (mixed) return vcycle<float>(c, 0, e32, r32, nullptr, true, first_done);
       return vcycle<double>(c, 0, kz, kr, nullptr, true, first_done);
     };
-    // FP64 preconditioning on a two-sweep finest grid: z.w comes out of its last pass
+    // FP64 preconditioning on a two-sweep finest grid: z.w comes out of its last pass,
+    // and, where the workspace holds a second residual, the residual update out of its first
     const bool zw_fused = !mixed && two_sweep_grid<double>(c, 0) && a.n > mg::kCoarseCycleMaxN;
+    const bool ru_fused = zw_fused && c->kr2 != nullptr;
+    double* kr_other = c->kr2;
     auto precondition_first_sweep = [&]() -> int {
       if (mixed) return first_sweep<float>(c, e32, r32, nullptr, true);
       return first_sweep<double>(c, kz, kr, nullptr, true);
@@ -456,13 +460,27 @@ int solve_one(mg_ctx* c, const double* f, double* p, double tol, int max_cycles,
     }
     while (std::isfinite(r) && r > tol && *cycles < max_cycles) {
       int nb = 0;
-      MG_HIP(mg::launch_fcg_rupdate(kr, kw, c->scal + S_DR, c->scal + S_DW, c->scal + S_ALPHA, q, kz_zero,
-                                    mixed ? r32 : nullptr, mixed ? e32_zero : nullptr, part(c, 2), &nb, c->stream));
+      if (ru_fused) {
+        // the preconditioner's first pass (z = 0 in, the finest grid's second buffer out)
+        // also forms r - alpha w, into the other residual buffer, and its norm
+        ZwSums ru{{}, &nb};
+        ru.x.w = kw;
+        ru.x.partials = part(c, 2);
+        ru.x.rnew = kr_other;
+        ru.x.s_dr = c->scal + S_DR;
+        ru.x.s_dw = c->scal + S_DW;
+        ru.x.s_alpha = c->scal + S_ALPHA;
+        MG_HIP(launch_two_sweeps<double>(c, 0, kz, a.t, kr, nullptr, MG_PRE, true, &ru));
+        std::swap(kr, kr_other);
+      } else {
+        MG_HIP(mg::launch_fcg_rupdate(kr, kw, c->scal + S_DR, c->scal + S_DW, c->scal + S_ALPHA, q, kz_zero,
+                                      mixed ? r32 : nullptr, mixed ? e32_zero : nullptr, part(c, 2), &nb, c->stream));
+      }
       MG_TRY(reduce_set(c, 2, nb, S_RNORM2));
       ++*cycles;
       double sn[8];
       MG_TRY(issue_scalars(c, 8));
-      ahead = spec && *cycles < max_cycles;
+      ahead = spec && *cycles < max_cycles && !ru_fused;
       if (ahead) MG_TRY(precondition_first_sweep());
       MG_TRY(wait_scalars(c, sn, 8));
       r = std::sqrt(sn[S_RNORM2]) / nf;
@@ -478,8 +496,10 @@ int solve_one(mg_ctx* c, const double* f, double* p, double tol, int max_cycles,
         break;
       }
       if (zw_fused) {   // z.w from the preconditioner's last pass
-        const ZwSums zw{kw, part(c, 3), &nb};
-        MG_TRY(vcycle<double>(c, 0, kz, kr, nullptr, true, ahead, &zw));
+        ZwSums zw{{}, &nb};
+        zw.x.w = kw;
+        zw.x.partials = part(c, 3);
+        MG_TRY(vcycle<double>(c, 0, kz, kr, nullptr, true, ahead || ru_fused, &zw));
       } else {
         MG_TRY(precondition(ahead));
         MG_HIP(mg::launch_fcg_zw(z64, z32, kw, q, part(c, 3), &nb, c->stream));
@@ -661,6 +681,7 @@ int setup_impl(mg_ctx** out, void* workspace, size_t ws_bytes, const double* bx,
   c->kd = at<double>(c->ws, plan.kd);
   c->kd2 = at<double>(c->ws, plan.kd2);
   c->kw = at<double>(c->ws, plan.kw);
+  c->kr2 = at<double>(c->ws, plan.kr2);
 
   auto cleanup = [&](int rc) {
     mg_destroy(c);
@@ -794,6 +815,7 @@ int make_lane(mg_ctx* ctx, unsigned char* ws, const mg::Plan& lp, int device, mg
   c->kd = at<double>(ws, lp.kd);
   c->kd2 = at<double>(ws, lp.kd2);
   c->kw = at<double>(ws, lp.kw);
+  c->kr2 = at<double>(ws, lp.kr2);
   *out = c;
   if (hipHostMalloc(reinterpret_cast<void**>(&c->host), sizeof(double) * S_COUNT, hipHostMallocDefault) != hipSuccess) {
     c->host = nullptr;
@@ -920,6 +942,7 @@ class ScratchSwap {
     kd_ = c->kd;
     kd2_ = c->kd2;
     kw_ = c->kw;
+    kr2_ = c->kr2;
     for (int l = 0; l < c->L; ++l) {
       Level& a = c->lv[l];
       const mg::LevelPlan& q = lp.lv[l];
@@ -939,6 +962,7 @@ class ScratchSwap {
     c->kd = at<double>(base, lp.kd);
     c->kd2 = at<double>(base, lp.kd2);
     c->kw = at<double>(base, lp.kw);
+    c->kr2 = at<double>(base, lp.kr2);
   }
   ~ScratchSwap() {
     for (int l = 0; l < c_->L; ++l) c_->lv[l] = saved_[l];
@@ -949,6 +973,7 @@ class ScratchSwap {
     c_->kd = kd_;
     c_->kd2 = kd2_;
     c_->kw = kw_;
+    c_->kr2 = kr2_;
   }
   ScratchSwap(const ScratchSwap&) = delete;
   ScratchSwap& operator=(const ScratchSwap&) = delete;
@@ -956,7 +981,7 @@ class ScratchSwap {
  private:
   mg_ctx* c_;
   Level saved_[mg::kMaxLevels];
-  double *partials_, *scal_, *kr_, *kz_, *kd_, *kd2_, *kw_;
+  double *partials_, *scal_, *kr_, *kz_, *kd_, *kd2_, *kw_, *kr2_;
 };
 
 }  // namespace

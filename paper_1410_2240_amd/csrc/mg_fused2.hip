@@ -78,12 +78,17 @@ __device__ __forceinline__ int ring_of(int r, int c) {
 __device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
-// ZW (FP64, post-smoothing of a flexible-CG preconditioner): also the workgroup's sum of
-// pout * w over its tile, the planes in order, into partials[blockIdx.x].
-template <typename T, bool ZIN, bool ZW>
+// W (FP64, flexible CG): the pass also reads w = A d and sums per workgroup, into
+// x.partials[blockIdx.x].  Post-smoothing of the preconditioner (not ZIN): the sum of
+// pout * w over the tile.  Its first pre-smoothing (ZIN, f = r): the residual update
+// r - alpha w (alpha = d.r / d.w) is formed where f is read and swept with, written to
+// x.rnew on the tile, and the sum is that of its squares.
+template <typename T, bool ZIN, bool W>
 __global__ __launch_bounds__(Shape<T>::TX / 2 * Shape<T>::TY) void k_rbgs_fused2(
     const T* __restrict__ pin, T* __restrict__ pout, const T* __restrict__ f, const T* __restrict__ rt, int q, int kc,
-    T h2, int first, const double* __restrict__ fshift, const double* __restrict__ w, double* __restrict__ partials) {
+    T h2, int first, const double* __restrict__ fshift, Fused2Extra x) {
+  constexpr bool ZW = W && !ZIN, RU = W && ZIN;
+  const double* __restrict__ w = x.w;
   using V2 = typename buf::Vec2<T>::type;
   constexpr int kTX = Shape<T>::TX, kTY = Shape<T>::TY;
   constexpr int kNT = kTX / 2 * kTY;          // one thread per tile x-pair
@@ -253,7 +258,30 @@ __global__ __launch_bounds__(Shape<T>::TX / 2 * Shape<T>::TY) void k_rbgs_fused2
   // on plane k, and the faces of the A1 and B1 updates for A2 and B2 two steps on
   // (tile), and of the ring's A1 for its A2
   T below_p[2] = {T(0), T(0)};
-  double zw = 0.0;   // ZW: this thread's sum of pout * w
+  double zw = 0.0;   // ZW: this thread's sum of pout * w; RU: of r_new^2 on its tile pair
+  // RU: alpha, and w of the owned pairs on the plane whose f came in the step before
+  const double alpha = RU ? *x.s_dr / *x.s_dw : 0.0;
+  if (RU && blockIdx.x == 0 && tid == 0) *x.s_alpha = alpha;
+  V2 wt{T(0), T(0)}, wg{T(0), T(0)};
+  auto load_w = [&](int kk) {
+    if constexpr (RU) {
+      const Rsrc wk = plane_rsrc(w, kk, q);
+      wt = ld2(wk, tf_off, T(0));
+      wg = has_ring ? ld2(wk, gf_off, T(0)) : V2{T(0), T(0)};
+    }
+  };
+  // RU: f of plane kk (in t, g) becomes r - alpha w (w in wt, wg); on the tile's own
+  // planes it is written out and its squares summed
+  auto update_r = [&](int kk, V2& t, V2& g) {
+    if constexpr (RU) {
+      t = V2{__builtin_fma(-alpha, wt.x, t.x), __builtin_fma(-alpha, wt.y, t.y)};
+      g = V2{__builtin_fma(-alpha, wg.x, g.x), __builtin_fma(-alpha, wg.y, g.y)};
+      if (kk >= k0 && kk < k1 && kk < n) {
+        *reinterpret_cast<V2*>(reinterpret_cast<char*>(x.rnew + (static_cast<long long>(kk) << (2 * q))) + tf_off) = t;
+        zw = __builtin_fma(t.y, t.y, __builtin_fma(t.x, t.x, zw));
+      }
+    }
+  };
   Faces ta[2], tb[2], ga[2];
 
   // ---- prologue: planes ks .. ks+3 staged (slots 0..3), ks+4 in registers, f of ks .. ks+3
@@ -268,7 +296,13 @@ __global__ __launch_bounds__(Shape<T>::TX / 2 * Shape<T>::TY) void k_rbgs_fused2
   store(ks + 3, integral_constant<int, 3>{});
   fetch(ks + 4);
 #pragma unroll
-  for (int d = 0; d < 4; ++d) load_f(ks + d, tfw[d], gfw[d]);
+  for (int d = 0; d < 4; ++d) {
+    load_f(ks + d, tfw[d], gfw[d]);
+    if constexpr (RU) {   // planes below the chunk: converted, not written; ks+3 in the first step
+      load_w(ks + d);
+      if (d < 3) update_r(ks + d, tfw[d], gfw[d]);
+    }
+  }
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
 
@@ -283,7 +317,9 @@ __global__ __launch_bounds__(Shape<T>::TX / 2 * Shape<T>::TY) void k_rbgs_fused2
     using S4 = integral_constant<int, (U + 4) % kSlots>;
     store(k + 4, S4{});
     fetch(k + 5);
+    if constexpr (RU) update_r(k + 3, tfw[S3::value], gfw[S3::value]);   // f and w came last step
     load_f(k + 4, tfw[S4::value], gfw[S4::value]);
+    if constexpr (RU) load_w(k + 4);
     V2 wk{T(0), T(0)};   // ZW: w of the tile pair on plane k, read while the step runs
     if constexpr (ZW) wk = ld2(plane_rsrc(w, k, q), tf_off, 0.0);
     __syncthreads();
@@ -343,7 +379,7 @@ __global__ __launch_bounds__(Shape<T>::TX / 2 * Shape<T>::TY) void k_rbgs_fused2
       step(k + 5, integral_constant<int, 5>{});
     }
   }
-  if constexpr (ZW) {   // the workgroup's sum: waves in order, through the first LDS words
+  if constexpr (W) {   // the workgroup's sum: waves in order, through the first LDS words
     for (int off = 32; off > 0; off >>= 1) zw += __shfl_xor(zw, off, 64);
     __syncthreads();   // every wave is past its last read of the staged planes
     double* red = reinterpret_cast<double*>(Pf);
@@ -352,7 +388,7 @@ __global__ __launch_bounds__(Shape<T>::TX / 2 * Shape<T>::TY) void k_rbgs_fused2
     if (tid == 0) {
       double s = 0.0;
       for (int v = 0; v < kNT / 64; ++v) s += red[v];
-      partials[blockIdx.x] = s;
+      x.partials[blockIdx.x] = s;
     }
   }
 }
@@ -363,40 +399,47 @@ int fused2_supported(int q) { return (1 << q) >= 256; }
 
 template <typename T>
 hipError_t launch_rbgs_fused2(const T* pin, T* pout, const T* f, const T* rt, int q, double h, int order,
-                              const double* fshift, int zero_in, hipStream_t s, const double* w, double* partials,
-                              int* nblocks) {
+                              const double* fshift, int zero_in, hipStream_t s, const Fused2Extra* x, int* nblocks) {
   constexpr int TX = Shape<T>::TX, TY = Shape<T>::TY;
   const int n = 1 << q;
   if (!fused2_supported(q) || !rt || pin == pout) return hipErrorInvalidValue;
-  const bool zw = w != nullptr;
-  if (zw && (sizeof(T) != 8 || zero_in || !partials || !nblocks)) return hipErrorInvalidValue;
+  const bool wx = x != nullptr && x->w != nullptr;
+  if (wx && (sizeof(T) != 8 || !x->partials || !nblocks)) return hipErrorInvalidValue;
+  if (wx && zero_in && (!x->rnew || static_cast<const void*>(x->rnew) == static_cast<const void*>(f) || !x->s_dr || !x->s_dw || !x->s_alpha || fshift))
+    return hipErrorInvalidValue;
   const long long tiles = static_cast<long long>(n / TX) * (n / TY);
   // z-chunks as long as possible while every compute unit still gets a workgroup
   int kc = n;
   while (kc > 8 && tiles * (n / kc) < 256) kc /= 2;
   const long long blocks = tiles * (n / kc);
-  if (zw && blocks > kNumPartials) return hipErrorInvalidValue;
+  if (wx && blocks > kNumPartials) return hipErrorInvalidValue;
   const T h2 = static_cast<T>(h * h);
   const int first = order == 0 ? 0 : 1;   // pre-smoothing: red first; post-smoothing: black first
   const dim3 grid(static_cast<unsigned>(blocks)), block(TX / 2 * TY);
-  if (zw) {
-    if constexpr (sizeof(T) == 8)
-      hipLaunchKernelGGL((k_rbgs_fused2<T, false, true>), grid, block, 0, s, pin, pout, f, rt, q, kc, h2, first,
-                         fshift, w, partials);
+  const Fused2Extra none{};
+  if (wx) {
+    if constexpr (sizeof(T) == 8) {
+      if (zero_in)
+        hipLaunchKernelGGL((k_rbgs_fused2<T, true, true>), grid, block, 0, s, pin, pout, f, rt, q, kc, h2, first,
+                           fshift, *x);
+      else
+        hipLaunchKernelGGL((k_rbgs_fused2<T, false, true>), grid, block, 0, s, pin, pout, f, rt, q, kc, h2, first,
+                           fshift, *x);
+    }
     *nblocks = static_cast<int>(blocks);
   } else if (zero_in) {
     hipLaunchKernelGGL((k_rbgs_fused2<T, true, false>), grid, block, 0, s, pin, pout, f, rt, q, kc, h2, first, fshift,
-                       nullptr, nullptr);
+                       none);
   } else {
     hipLaunchKernelGGL((k_rbgs_fused2<T, false, false>), grid, block, 0, s, pin, pout, f, rt, q, kc, h2, first,
-                       fshift, nullptr, nullptr);
+                       fshift, none);
   }
   return hipGetLastError();
 }
 
 template hipError_t launch_rbgs_fused2<float>(const float*, float*, const float*, const float*, int, double, int,
-                                              const double*, int, hipStream_t, const double*, double*, int*);
+                                              const double*, int, hipStream_t, const Fused2Extra*, int*);
 template hipError_t launch_rbgs_fused2<double>(const double*, double*, const double*, const double*, int, double, int,
-                                               const double*, int, hipStream_t, const double*, double*, int*);
+                                               const double*, int, hipStream_t, const Fused2Extra*, int*);
 
 }  // namespace mg

@@ -131,15 +131,26 @@ template <typename T>
 hipError_t launch_rbgs_box_prolong(const T* pin, T* pout, const T* f, const T* bx, const T* by, const T* bz, int q,
                                    double h, int order, const double* fshift, const T* ec, const uint8_t* mask,
                                    hipStream_t s);
+// What the FP64 two-sweep pass of flexible CG does besides its sweeps (w null: nothing).
+struct Fused2Extra {
+  const double* w = nullptr;        // w = A d of the current direction
+  double* partials = nullptr;       // one partial sum per workgroup (see below)
+  double* rnew = nullptr;           // residual update: r - alpha w, written here
+  const double* s_dr = nullptr;     // residual update: alpha = *s_dr / *s_dw,
+  const double* s_dw = nullptr;
+  double* s_alpha = nullptr;        // also stored here
+};
 // Two red-black sweeps in one pass (density form, grids of 256^3 and up): pin -> pout
-// (distinct), order as launch_rbgs_fused; bit for bit two one-pass sweeps.  With w
-// (FP64, not zero_in): also one partial sum of pout * w per workgroup into partials,
-// their number into *nblocks (at most kNumPartials).
+// (distinct), order as launch_rbgs_fused; bit for bit two one-pass sweeps.  With x->w
+// (FP64): one partial sum per workgroup into x->partials, their number into *nblocks
+// (at most kNumPartials); without zero_in the sum is pout . w; with zero_in (the first
+// pre-smoothing of a preconditioner, f = r, no fshift) the pass sweeps with and writes
+// r - alpha w to x->rnew (not f), and the sum is its squared norm.
 int fused2_supported(int q);
 template <typename T>
 hipError_t launch_rbgs_fused2(const T* pin, T* pout, const T* f, const T* rt, int q, double h, int order,
-                              const double* fshift, int zero_in, hipStream_t s, const double* w = nullptr,
-                              double* partials = nullptr, int* nblocks = nullptr);
+                              const double* fshift, int zero_in, hipStream_t s, const Fused2Extra* x = nullptr,
+                              int* nblocks = nullptr);
 template <typename T>
 hipError_t launch_rbgs_fused(const T* pin, T* pout, const T* f, const T* bx, const T* by, const T* bz, const T* rt,
                              int q, double h, int order, const double* fshift, int zero_in, hipStream_t s);
