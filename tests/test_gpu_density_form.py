@@ -84,14 +84,15 @@ def test_fcg_bitwise():
     assert torch.equal(pa, pb)
 
 
-def test_fcg_256_fused_zw_follows_the_separate_pass():
-    """On a 256^3 grid set up from rho, the FP64 preconditioning cycle ends in the
-    two-sweep pass, which also sums flexible CG's z.w as it writes z; set up from face
-    arrays, the grid sweeps once per pass and z.w has a pass of its own.  All else is
-    bit for bit the same, so the two solves differ only in the order of that sum's
-    terms: histories equal to rounding, the same solution."""
+def test_fcg_256_fused_passes_follow_the_separate_ones():
+    """On a 256^3 grid set up from rho, the FP64 preconditioning cycle starts with a
+    two-sweep pass that also updates flexible CG's residual (r - alpha w, and its norm)
+    and ends with one that also sums z.w as it writes z; set up from face arrays, the
+    grid sweeps once per pass and the update and z.w have passes of their own.  The
+    updated residual is the same bit for bit; the two solves differ only in the order
+    of the two sums' terms: histories equal to rounding, the same solution."""
     inp, a, b = pair(256, krylov=True)
-    print("density-form FCG 256: fused z.w against its own pass", flush=True)
+    print("density-form FCG 256: fused residual update and z.w against their own passes", flush=True)
     f = dev(inp.f)
     pa, ha, sa = a.solve(f, tol=1e-10, max_cycles=60)
     pb, hb, sb = b.solve(f, tol=1e-10, max_cycles=60)
