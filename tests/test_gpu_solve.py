@@ -204,7 +204,8 @@ def test_mixed_batch_and_warm_start_64():
 
 
 @pytest.mark.parametrize("N,mixed,krylov,lanes", [(64, False, False, 2), (64, True, False, 2), (64, False, True, 3),
-                                                  (64, True, True, 2), (32, False, False, 1), (128, False, False, 3)])
+                                                  (64, True, True, 2), (32, False, False, 1), (128, False, False, 3),
+                                                  (256, False, True, 2)])
 def test_lanes_give_the_one_by_one_results(N, mixed, krylov, lanes):
     """A batch solved on 1 + lanes concurrent streams: every item's solution and history
     bit for bit those of the one-at-a-time loop (five items, so lanes get unequal
