@@ -60,7 +60,10 @@ constexpr double kBreakdownGrowth = 1e3;
 constexpr double kZeroRhs = 64.0 * 2.220446049250313e-16;
 
 // device scalar slots
-enum { S_FMEAN = 0, S_FNORM2 = 1, S_RNORM2 = 2, S_PMEAN = 3, S_DW = 4, S_DR = 5, S_ZW = 6, S_ALPHA = 7, S_COUNT = 8 };
+enum {
+  S_FMEAN = 0, S_FNORM2 = 1, S_RNORM2 = 2, S_PMEAN = 3, S_DW = 4, S_DR = 5, S_ZW = 6, S_ALPHA = 7, S_ALPHA_PREV = 8,
+  S_COUNT = 9
+};
 
 struct Level {
   int n = 0, q = 0;
@@ -93,6 +96,7 @@ struct mg_ctx {
   long long* counters = nullptr;
   double *kr = nullptr, *kz = nullptr, *kd = nullptr, *kd2 = nullptr, *kw = nullptr;   // flexible-CG vectors
   double* kr2 = nullptr;   // a second residual (absent unless the plan holds one)
+  double* kd3 = nullptr;   // a third direction (likewise)
   double* host = nullptr;   // pinned, S_COUNT doubles
   hipEvent_t read_done = nullptr;   // the last read-back of scalars has landed in host
   long long active = 0, dropped = 0;
@@ -412,8 +416,14 @@ int solve_one(mg_ctx* c, const double* f, double* p, double tol, int max_cycles,
     // -z.w / d.w) in the other direction buffer, w = A d', d'.w and d'.r, and the update
     // p += alpha d deferred from the step before (the last one is applied on exit).
     double *kr = c->kr, *kz = c->kz, *kw = c->kw;
-    double* dirs[2] = {c->kd, c->kd2};
+    // p's update every second step where the workspace holds a third direction: the
+    // step that skips it leaves its direction in place for the next one (three buffers
+    // in turn instead of two)
+    const bool defer = c->kd3 != nullptr && mg::fcgx_defer_supported(a.rt, a.q);
+    double* dirs[3] = {c->kd, c->kd2, c->kd3};
     int cur = 0;   // dirs[cur] holds the current direction
+    auto next_dir = [&](int i) { return defer ? (i + 1) % 3 : 1 - i; };
+    int nx = 0;    // direction passes after the first
     const int q = a.q;
     const float* z32 = mixed ? e32 : nullptr;
     const double* z64 = mixed ? nullptr : kz;
@@ -435,18 +445,31 @@ int solve_one(mg_ctx* c, const double* f, double* p, double tol, int max_cycles,
     auto direction = [&](bool first) -> int {
       const double* s_zw = first ? nullptr : c->scal + S_ZW;
       const double* s_dw = first ? nullptr : c->scal + S_DW;
-      double* dnew = dirs[1 - cur];
+      double* dnew = dirs[next_dir(cur)];
       int nb = 0;
       if (mg::march_supported(q)) {
+        mg::FcgxDefer df;
+        const bool use_df = defer && !first;
+        if (use_df) {
+          ++nx;
+          if (nx & 1) {   // this step's update of p waits for the next one
+            df.skip = true;
+            df.s_alpha_save = c->scal + S_ALPHA_PREV;
+          } else {        // the one the step before left, then this one
+            df.d_prev = dirs[(cur + 2) % 3];
+            df.s_alpha_prev = c->scal + S_ALPHA_PREV;
+          }
+        }
         MG_HIP(mg::launch_fcg_x_march(z64, z32, dirs[cur], dnew, p, s_zw, s_dw, c->scal + S_ALPHA, kr, a.bx, a.by,
-                                      a.bz, a.rt, q, a.h, kw, part(c, 0), part(c, 1), &nb, c->stream));
+                                      a.bz, a.rt, q, a.h, kw, part(c, 0), part(c, 1), &nb, c->stream,
+                                      use_df ? &df : nullptr));
       } else {
         MG_HIP(mg::launch_fcg_dir(z64, z32, dirs[cur], dnew, first ? nullptr : p, s_zw, s_dw, c->scal + S_ALPHA, q,
                                   c->stream));
         MG_HIP(mg::launch_fcg_aw(dnew, kr, a.bx, a.by, a.bz, a.rt, q, a.h, kw, part(c, 0), part(c, 1), &nb,
                                  c->stream));
       }
-      cur = 1 - cur;
+      cur = next_dir(cur);
       MG_TRY(reduce_set(c, 0, nb, S_DW));
       MG_TRY(reduce_set(c, 1, nb, S_DR));
       return MG_OK;
@@ -489,7 +512,12 @@ int solve_one(mg_ctx* c, const double* f, double* p, double tol, int max_cycles,
       const bool broke = !std::isfinite(r) || !(sn[S_DW] < 0.0) || r > kBreakdownGrowth * std::fmax(r0, 1.0);
       if (broke || r <= tol || *cycles >= max_cycles) {
         // p += alpha d of this step, which the next direction pass would have applied
-        MG_HIP(mg::launch_fcg_padd(p, dirs[cur], c->scal + S_ALPHA, q, c->stream));
+        // (after the update the last direction pass left, if it left one)
+        if (defer && (nx & 1))
+          MG_HIP(mg::launch_fcg_padd2(p, dirs[(cur + 2) % 3], c->scal + S_ALPHA_PREV, dirs[cur], c->scal + S_ALPHA, q,
+                                      c->stream));
+        else
+          MG_HIP(mg::launch_fcg_padd(p, dirs[cur], c->scal + S_ALPHA, q, c->stream));
         if (broke)
           status = fail(MG_EBREAKDOWN, "flexible CG breakdown after %d steps (residual %g, d.Ad %g)", *cycles, r,
                         sn[S_DW]);
@@ -682,6 +710,7 @@ int setup_impl(mg_ctx** out, void* workspace, size_t ws_bytes, const double* bx,
   c->kd2 = at<double>(c->ws, plan.kd2);
   c->kw = at<double>(c->ws, plan.kw);
   c->kr2 = at<double>(c->ws, plan.kr2);
+  c->kd3 = at<double>(c->ws, plan.kd3);
 
   auto cleanup = [&](int rc) {
     mg_destroy(c);
@@ -816,6 +845,7 @@ int make_lane(mg_ctx* ctx, unsigned char* ws, const mg::Plan& lp, int device, mg
   c->kd2 = at<double>(ws, lp.kd2);
   c->kw = at<double>(ws, lp.kw);
   c->kr2 = at<double>(ws, lp.kr2);
+  c->kd3 = at<double>(ws, lp.kd3);
   *out = c;
   if (hipHostMalloc(reinterpret_cast<void**>(&c->host), sizeof(double) * S_COUNT, hipHostMallocDefault) != hipSuccess) {
     c->host = nullptr;
@@ -943,6 +973,7 @@ class ScratchSwap {
     kd2_ = c->kd2;
     kw_ = c->kw;
     kr2_ = c->kr2;
+    kd3_ = c->kd3;
     for (int l = 0; l < c->L; ++l) {
       Level& a = c->lv[l];
       const mg::LevelPlan& q = lp.lv[l];
@@ -963,6 +994,7 @@ class ScratchSwap {
     c->kd2 = at<double>(base, lp.kd2);
     c->kw = at<double>(base, lp.kw);
     c->kr2 = at<double>(base, lp.kr2);
+    c->kd3 = at<double>(base, lp.kd3);
   }
   ~ScratchSwap() {
     for (int l = 0; l < c_->L; ++l) c_->lv[l] = saved_[l];
@@ -974,6 +1006,7 @@ class ScratchSwap {
     c_->kd2 = kd2_;
     c_->kw = kw_;
     c_->kr2 = kr2_;
+    c_->kd3 = kd3_;
   }
   ScratchSwap(const ScratchSwap&) = delete;
   ScratchSwap& operator=(const ScratchSwap&) = delete;
@@ -981,7 +1014,7 @@ class ScratchSwap {
  private:
   mg_ctx* c_;
   Level saved_[mg::kMaxLevels];
-  double *partials_, *scal_, *kr_, *kz_, *kd_, *kd2_, *kw_, *kr2_;
+  double *partials_, *scal_, *kr_, *kz_, *kd_, *kd2_, *kw_, *kr2_, *kd3_;
 };
 
 }  // namespace

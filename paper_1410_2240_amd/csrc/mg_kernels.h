@@ -212,10 +212,23 @@ hipError_t launch_fcg_aw_march(const double* d, const double* r, const double* b
 // and d is not used), w = A dn, partial sums of dn.w and dn.r, and p += *s_alpha d
 // (the previous step's update, skipped on the first step).  z is z64 or z32 (exactly
 // one non-null); dn must not be d.
+// With df (density-form grids of 128^3 and up, not the first step), p's update every
+// second step: df->skip leaves this step's update to the next one (p is not touched,
+// *s_alpha is saved to df->s_alpha_save); otherwise p += *df->s_alpha_prev df->d_prev
+// (the update left by the step before, d_prev distinct from d and dn) and then
+// p += *s_alpha d, the same operations in the same order as two steps apart.
+struct FcgxDefer {
+  bool skip = false;
+  double* s_alpha_save = nullptr;
+  const double* d_prev = nullptr;
+  const double* s_alpha_prev = nullptr;
+};
+int fcgx_defer_supported(const double* rt, int q);
 hipError_t launch_fcg_x_march(const double* z64, const float* z32, const double* d, double* dn, double* p,
                               const double* s_zw, const double* s_dw, const double* s_alpha, const double* r,
                               const double* bx, const double* by, const double* bz, const double* rt, int q, double h,
-                              double* w, double* part_dw, double* part_dr, int* nblocks, hipStream_t s);
+                              double* w, double* part_dw, double* part_dr, int* nblocks, hipStream_t s,
+                              const FcgxDefer* df = nullptr);
 
 // ---- FP64 finest-grid passes ------------------------------------------------------
 // partials[blockIdx] = sum over active cells of r^2, r = (f - fshift) - A p; optional
@@ -236,6 +249,9 @@ hipError_t launch_fcg_rupdate(double* r, const double* w, const double* s_dr, co
                               int q, double* z_zero, float* r32, float* e32_zero, double* part_rr, int* nblocks,
                               hipStream_t s);
 hipError_t launch_fcg_padd(double* p, const double* d, const double* s_alpha, int q, hipStream_t s);
+// p += *s_alpha0 d0, then p += *s_alpha d (two updates left pending, in their order)
+hipError_t launch_fcg_padd2(double* p, const double* d0, const double* s_alpha0, const double* d, const double* s_alpha,
+                            int q, hipStream_t s);
 hipError_t launch_fcg_zw(const double* z64, const float* z32, const double* w, int q, double* part, int* nblocks,
                          hipStream_t s);
 hipError_t launch_fcg_dir(const double* z64, const float* z32, const double* d, double* dn, double* p,

@@ -946,6 +946,17 @@ __global__ __launch_bounds__(kBlock) void k_fcg_padd(double* __restrict__ p, con
   *reinterpret_cast<double2*>(p + c) = double2{fmad(alpha, dv.x, pv.x), fmad(alpha, dv.y, pv.y)};
 }
 
+__global__ __launch_bounds__(kBlock) void k_fcg_padd2(double* __restrict__ p, const double* __restrict__ d0,
+                                                      const double* __restrict__ s_alpha0, const double* __restrict__ d,
+                                                      const double* __restrict__ s_alpha, int total) {
+  const double alpha0 = *s_alpha0, alpha = *s_alpha;
+  const long long c = 2 * (static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x);
+  if (c >= total) return;
+  const double2 pv = ld2(p, static_cast<int>(c)), ov = ld2(d0, static_cast<int>(c)), dv = ld2(d, static_cast<int>(c));
+  *reinterpret_cast<double2*>(p + c) =
+      double2{fmad(alpha, dv.x, fmad(alpha0, ov.x, pv.x)), fmad(alpha, dv.y, fmad(alpha0, ov.y, pv.y))};
+}
+
 // partial sums of z.w, z in FP64 (z64) or FP32 (z32)
 __global__ __launch_bounds__(kBlock) void k_fcg_zw(const double* __restrict__ z64, const float* __restrict__ z32,
                                                    const double* __restrict__ w, int total,
@@ -1220,6 +1231,13 @@ hipError_t launch_fcg_rupdate(double* r, const double* w, const double* s_dr, co
 
 hipError_t launch_fcg_padd(double* p, const double* d, const double* s_alpha, int q, hipStream_t s) {
   hipLaunchKernelGGL(k_fcg_padd, dim3(grid_for(1LL << (3 * q - 1))), dim3(kBlock), 0, s, p, d, s_alpha, 1 << (3 * q));
+  return hipGetLastError();
+}
+
+hipError_t launch_fcg_padd2(double* p, const double* d0, const double* s_alpha0, const double* d, const double* s_alpha,
+                            int q, hipStream_t s) {
+  hipLaunchKernelGGL(k_fcg_padd2, dim3(grid_for(1LL << (3 * q - 1))), dim3(kBlock), 0, s, p, d0, s_alpha0, d, s_alpha,
+                     1 << (3 * q));
   return hipGetLastError();
 }
 

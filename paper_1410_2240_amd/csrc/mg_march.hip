@@ -82,6 +82,11 @@ struct MarchArgs {
   const double* s_alpha;
   double* dn;
   double* pp;
+  // FCGX through LDS, p's update every second step: p += *s_alpha_prev dprev first (the
+  // update the step before left), and *s_alpha saved to s_alpha_save (a step that leaves it)
+  const double* dprev;
+  const double* s_alpha_prev;
+  double* s_alpha_save;
 };
 
 // The six faces of the two cells of an x-pair
@@ -587,6 +592,7 @@ __global__ __launch_bounds__(kMarchThreads) void k_fcgx_lds(MarchArgs<double> a)
   const T inf = __builtin_huge_val();
   const T zero = T(0);
   const int tid = threadIdx.x;
+  if (a.s_alpha_save && blockIdx.x == 0 && tid == 0) *a.s_alpha_save = *a.s_alpha;
   const int G = gridDim.x, bid = blockIdx.x;
   const int lid = (G % 8 == 0) ? (bid % 8) * (G / 8) + bid / 8 : bid;   // neighbours on one XCD
   const int ntx = n / TX, nty = n / TY;
@@ -754,8 +760,14 @@ __global__ __launch_bounds__(kMarchThreads) void k_fcgx_lds(MarchArgs<double> a)
     stream_store(a.dn + cb, cur.pb);
     if (a.pp) {
       const double alpha = *a.s_alpha;
-      const V2 xa = *reinterpret_cast<const V2*>(a.pp + ca);
-      const V2 xb = *reinterpret_cast<const V2*>(a.pp + cb);
+      V2 xa = *reinterpret_cast<const V2*>(a.pp + ca);
+      V2 xb = *reinterpret_cast<const V2*>(a.pp + cb);
+      if (a.dprev) {   // the step before's update first, as it would have been applied
+        const double alpha0 = *a.s_alpha_prev;
+        const V2 oa = *reinterpret_cast<const V2*>(a.dprev + ca), ob = *reinterpret_cast<const V2*>(a.dprev + cb);
+        xa = V2{__builtin_fma(alpha0, oa.x, xa.x), __builtin_fma(alpha0, oa.y, xa.y)};
+        xb = V2{__builtin_fma(alpha0, ob.x, xb.x), __builtin_fma(alpha0, ob.y, xb.y)};
+      }
       stream_store(a.pp + ca, V2{__builtin_fma(alpha, cur.da.x, xa.x), __builtin_fma(alpha, cur.da.y, xa.y)});
       stream_store(a.pp + cb, V2{__builtin_fma(alpha, cur.db.x, xb.x), __builtin_fma(alpha, cur.db.y, xb.y)});
     }
@@ -811,6 +823,7 @@ hipError_t launch_form(MarchArgs<T> a, int* nblocks, hipStream_t s) {
 }  // namespace
 
 int march_supported(int q) { return (1 << q) >= 32; }
+int fcgx_defer_supported(const double* rt, int q) { return rt != nullptr && (1 << q) >= 128; }
 
 hipError_t launch_residual_norm_march(const double* p, const double* f, const double* bx, const double* by,
                                       const double* bz, const double* rt, int q, double h, const double* fshift,
@@ -910,8 +923,13 @@ hipError_t launch_fcg_aw_march(const double* d, const double* r, const double* b
 hipError_t launch_fcg_x_march(const double* z64, const float* z32, const double* d, double* dn, double* p,
                               const double* s_zw, const double* s_dw, const double* s_alpha, const double* r,
                               const double* bx, const double* by, const double* bz, const double* rt, int q, double h,
-                              double* w, double* part_dw, double* part_dr, int* nblocks, hipStream_t s) {
+                              double* w, double* part_dw, double* part_dr, int* nblocks, hipStream_t s,
+                              const FcgxDefer* df) {
   if ((z64 == nullptr) == (z32 == nullptr) || !d || !dn || dn == d || (s_zw == nullptr) != (s_dw == nullptr))
+    return hipErrorInvalidValue;
+  if (df && (!fcgx_defer_supported(rt, q) || !s_zw || (df->skip ? !df->s_alpha_save
+                                                                : (!df->d_prev || !df->s_alpha_prev ||
+                                                                   df->d_prev == dn || df->d_prev == d))))
     return hipErrorInvalidValue;
   MarchArgs<double> a{};
   a.p = d;
@@ -932,6 +950,15 @@ hipError_t launch_fcg_x_march(const double* z64, const float* z32, const double*
   a.s_alpha = s_alpha;
   a.dn = dn;
   a.pp = s_zw ? p : nullptr;
+  if (df) {
+    if (df->skip) {
+      a.pp = nullptr;
+      a.s_alpha_save = df->s_alpha_save;
+    } else {
+      a.dprev = df->d_prev;
+      a.s_alpha_prev = df->s_alpha_prev;
+    }
+  }
   if (rt && (1 << q) >= 128) {   // the density form: the stencil through LDS
     const int n = 1 << q;
     const long long tiles = static_cast<long long>(n / 128) * (n / 8);

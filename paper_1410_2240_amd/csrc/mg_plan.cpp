@@ -82,6 +82,7 @@ int build_plan(int n, int flags, Plan* plan) {
     p.kd2 = c.take(fine);
     p.kw = c.take(fine);
     if (plan_has_kr2(n, flags)) p.kr2 = c.take(fine);
+    if (plan_has_kd3(n, flags)) p.kd3 = c.take(fine);
   }
   const size_t nc = static_cast<size_t>(kCoarsest) * kCoarsest * kCoarsest;
   p.pinv = c.take(nc * nc * 8);
@@ -128,6 +129,7 @@ int build_lane_plan(int n, int flags, Plan* plan) {
     p.kd2 = c.take(fine);
     p.kw = c.take(fine);
     if (plan_has_kr2(n, flags)) p.kr2 = c.take(fine);
+    if (plan_has_kd3(n, flags)) p.kd3 = c.take(fine);
   }
   p.pinv = kAbsent;
   p.partials = c.take(static_cast<size_t>(kPartialSets) * kNumPartials * 8);

@@ -41,10 +41,11 @@ struct LevelPlan {
   size_t f32 = 0, e32 = 0, t32 = 0;
 };
 
-// the second residual kr2 of a flexible-CG plan
+// the second residual kr2 and the third direction kd3 of a flexible-CG plan
 inline bool plan_has_kr2(int n, int flags) {
   return (flags & kFlagKrylov) && !(flags & kFlagMixed) && (flags & kFlagFromRho) && n >= 256;
 }
+inline bool plan_has_kd3(int n, int flags) { return (flags & kFlagKrylov) && (flags & kFlagFromRho) && n >= 128; }
 
 struct Plan {
   int n = 0;
@@ -54,8 +55,10 @@ struct Plan {
   // finest-grid FP64 vectors of the flexible-CG outer iteration (Krylov flag only):
   // residual, preconditioned residual, two directions (old and new), and A d; kr2, a
   // second residual, only for FP64 setups from rho on grids of 256^3 and up, whose
-  // preconditioner's first pass forms the updated residual out of place
-  size_t kr = kAbsent, kz = kAbsent, kd = kAbsent, kd2 = kAbsent, kw = kAbsent, kr2 = kAbsent;
+  // preconditioner's first pass forms the updated residual out of place; kd3, a third
+  // direction, for setups from rho on grids of 128^3 and up, which update p every
+  // second step (the direction of the step before is still needed then)
+  size_t kr = kAbsent, kz = kAbsent, kd = kAbsent, kd2 = kAbsent, kw = kAbsent, kr2 = kAbsent, kd3 = kAbsent;
   size_t pinv = 0;       // (4^3)^2 doubles: pseudo-inverse of the coarsest operator
   size_t partials = 0;   // kPartialSets x kNumPartials doubles
   size_t scalars = 0;    // 32 doubles of device scalars

@@ -73,6 +73,9 @@ static void check_layout(int n, int flags) {
   // the second residual: FP64 flexible CG from rho on grids of 256^3 and up only
   if ((flags & 2) && !(flags & 1) && (flags & mg::kFlagFromRho) && n >= 256) spans.push_back({p.kr2, fine});
   else CHECK(p.kr2 == mg::kAbsent);
+  // the third direction: flexible CG from rho on grids of 128^3 and up
+  if ((flags & 2) && (flags & mg::kFlagFromRho) && n >= 128) spans.push_back({p.kd3, fine});
+  else CHECK(p.kd3 == mg::kAbsent);
   spans.push_back({p.pinv, 64 * 64 * 8});
   spans.push_back({p.partials, static_cast<size_t>(mg::kPartialSets) * mg::kNumPartials * 8});
   spans.push_back({p.scalars, 32 * 8});
@@ -123,6 +126,9 @@ static void check_lane_layout(int n, int flags) {
   // the second residual: FP64 flexible CG from rho on grids of 256^3 and up only
   if ((flags & 2) && !(flags & 1) && (flags & mg::kFlagFromRho) && n >= 256) spans.push_back({p.kr2, fine});
   else CHECK(p.kr2 == mg::kAbsent);
+  // the third direction: flexible CG from rho on grids of 128^3 and up
+  if ((flags & 2) && (flags & mg::kFlagFromRho) && n >= 128) spans.push_back({p.kd3, fine});
+  else CHECK(p.kd3 == mg::kAbsent);
   CHECK(p.pinv == mg::kAbsent && p.counters == mg::kAbsent);
   spans.push_back({p.partials, static_cast<size_t>(mg::kPartialSets) * mg::kNumPartials * 8});
   spans.push_back({p.scalars, 32 * 8});
