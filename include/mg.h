@@ -71,8 +71,8 @@ enum {
                     V(2,2) cycle per step (FP32 cycle with MG_MIXED); all vector updates
                     and dot products FP64.  Removes the few error modes a V-cycle misses
                     at steep, non-grid-aligned density interfaces.  Five more FP64
-                    finest-grid vectors in the workspace (six with MG_FROM_RHO, see
-                    there). */
+                    finest-grid vectors in the workspace (up to seven with MG_FROM_RHO,
+                    see there). */
   MG_COARSEN_DENSITY = 4, /* mg_setup_from_rho only: the coarsening section 3.1 rejects -
                     density restricted cell centre to cell centre (mean over active
                     children), open areas restricted separately (mean of 4 faces), and
@@ -82,11 +82,12 @@ enum {
                     both): the workspace is for a setup from the density, so an MG_MIXED
                     context on a grid of 64^3 and up leaves out the FP32 face arrays of its
                     finest grid, which its FP32 cycles form from the density instead (12
-                    bytes per cell less); an FP64 MG_KRYLOV context on a grid of 256^3 and
-                    up gets a second residual vector (8 bytes per cell more), with which its
-                    preconditioner's first pass also updates the residual, in place of a
-                    pass of its own.  Without it the size covers both setups (and the
-                    residual update keeps its own pass). */
+                    bytes per cell less); an MG_KRYLOV context on a grid of 128^3 and up
+                    gets a third direction vector, with which it updates the solution every
+                    second step, and in FP64 on a grid of 256^3 and up a second residual,
+                    with which its preconditioner's first pass also updates the residual
+                    in place of a pass of its own (8 bytes per cell more each).  Without it
+                    the size covers both setups (and those updates keep their passes). */
 };
 
 /* precision selector of the component entry points */
