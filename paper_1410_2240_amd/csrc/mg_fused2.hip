@@ -33,8 +33,14 @@
 // A2 from k0-1, B2 from k0 (all within the grid), recomputing what the chunk below
 // computes on those planes from the same inputs, so chunks need no communication.
 // The arithmetic of every update (the faces face_beta(rt_L, rt_R), their sum, the fused
-// multiply-adds in a fixed order and the division) is that of the one-pass sweep, so two
+// multiply-adds in a fixed order and the quotient) is that of the one-pass sweep, so two
 // sweeps of either kernel give the same bits.
+//
+// In FP64 flexible CG the two passes of the preconditioner's finest grid also take two
+// of the outer iteration's vector passes, reading w = A d as they go: the first
+// (pre-smoothing from zero, f = r) forms the residual update r - alpha w where it reads
+// f, sweeps with it, writes it out of place and sums its squares; the last
+// (post-smoothing, writing z) sums z.w.  Each sum is one partial per workgroup.
 #include <type_traits>
 
 #include "mg_buffer.h"
