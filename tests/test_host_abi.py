@@ -53,6 +53,14 @@ def test_workspace_size_is_host_arithmetic():
     assert lib.mg_workspace_size(_lib.dims3(64), 4) == lib.mg_workspace_size(_lib.dims3(64), 0)
     # a mixed setup from the density leaves out the FP32 face arrays of the finest grid
     assert s32 - lib.mg_workspace_size(_lib.dims3(256), 1 | _lib.MG_FROM_RHO) >= 3 * n * 4
+    # flexible CG from the density: a third direction (128^3 and up) and, in FP64 (256^3
+    # and up), a second residual; the mixed workspace still drops its FP32 finest faces
+    ws = lambda N, fl: lib.mg_workspace_size(_lib.dims3(N), fl)
+    K, R, M = _lib.MG_KRYLOV, _lib.MG_FROM_RHO, _lib.MG_MIXED
+    assert ws(256, K | R) - ws(256, K) == 2 * n * 8
+    assert ws(256, K | M) - ws(256, K | M | R) == 3 * n * 4 - n * 8
+    assert ws(128, K | R) - ws(128, K) == 128 ** 3 * 8
+    assert ws(64, K | R) == ws(64, K)
     # one concurrent right-hand side's scratch: every grid's f, e and second buffer
     # (the finest grid's f and e are the caller's), without the coefficients
     lane = lib.mg_lane_workspace_size(_lib.dims3(256), 0)
