@@ -248,6 +248,17 @@ __global__ __launch_bounds__(Shape<T>::TX / 2 * Shape<T>::TY) void k_rbgs_fused2
     return Faces{face_beta(Rf[S + x.left], rc), face_beta(rc, Rf[S + x.left + 1]),
                  face_beta(Rf[S + x.own - kRow], rc), face_beta(rc, Rf[S + x.own + kRow]), zm, zp};
   };
+  // FP64 (registers to spare): the x face between a pair's two cells on a plane is formed
+  // by the A1 update of one column and needed again by the B1 update of the other column
+  // on the same plane a step later, so it is kept for it (one face fewer per step).
+  constexpr bool kXKeep = sizeof(T) == 8;
+  auto faces_b1x = [&](auto s_tag, const Cell& x, T zm, T zp, T xpair, bool odd) {
+    constexpr int S = decltype(s_tag)::value * kSlot;
+    const T rc = Rf[S + x.own];
+    const T xo = face_beta(rc, Rf[S + (odd ? x.left + 1 : x.left)]);   // the face away from the partner
+    return Faces{odd ? xpair : xo, odd ? xo : xpair, face_beta(Rf[S + x.own - kRow], rc),
+                 face_beta(rc, Rf[S + x.own + kRow]), zm, zp};
+  };
   auto gs = [&](auto s_tag, auto sa_tag, const Cell& x, const Faces& F, T lo_p, T fv) {
     constexpr int S = decltype(s_tag)::value * kSlot, SA = decltype(sa_tag)::value * kSlot;
     const T D = F.xm + F.xp + F.ym + F.yp + F.zm + F.zp;
@@ -289,6 +300,7 @@ __global__ __launch_bounds__(Shape<T>::TX / 2 * Shape<T>::TY) void k_rbgs_fused2
     }
   };
   Faces ta[2], tb[2], ga[2];
+  T xt = T(0), xg = T(0);   // the pair's x face kept from the step before (tile, ring)
 
   // ---- prologue: planes ks .. ks+3 staged (slots 0..3), ks+4 in registers, f of ks .. ks+3
   const int ks = k0 - 6;   // even: chunks start at multiples of kc >= 8
@@ -335,10 +347,13 @@ __global__ __launch_bounds__(Shape<T>::TX / 2 * Shape<T>::TY) void k_rbgs_fused2
       const bool odd = todd[PAR];
       const Faces a2f = ta[PAR], b2f = tb[PAR];   // from step k-2, before this step's A1, B1
       ta[PAR] = faces(S3{}, S4{}, c, Rf[S2::value * kSlot + c.own]);
+      const T xprev = xt;
+      if constexpr (kXKeep) xt = odd ? ta[PAR].xm : ta[PAR].xp;
       if (ka >= lo_a1 && ka < n)
         gs(S3{}, S4{}, c, ta[PAR], Pf[S2::value * kSlot + c.own], odd ? tfw[S3::value].y : tfw[S3::value].x);
       if (kb >= lo_b1 && kb < n) {
-        tb[PAR] = faces_b1(S2{}, c, a2f.zp, ta[PAR].zm);
+        if constexpr (kXKeep) tb[PAR] = faces_b1x(S2{}, c, a2f.zp, ta[PAR].zm, xprev, odd);
+        else tb[PAR] = faces_b1(S2{}, c, a2f.zp, ta[PAR].zm);
         gs(S2{}, S3{}, c, tb[PAR], Pf[S1::value * kSlot + c.own], odd ? tfw[S2::value].y : tfw[S2::value].x);
       }
       if (kA >= lo_a2 && kA < n)
@@ -360,14 +375,19 @@ __global__ __launch_bounds__(Shape<T>::TX / 2 * Shape<T>::TY) void k_rbgs_fused2
       const bool odd = godd[PAR];
       const int d = gd[PAR];
       const Faces a2f = ga[PAR];
-      if (d <= 3) {
+      const T xgprev = xg;
+      if (d <= 3) {   // every ring pair's columns are within 3 cells of the tile
         ga[PAR] = faces(S3{}, S4{}, c, Rf[S2::value * kSlot + c.own]);
+        if constexpr (kXKeep) xg = odd ? ga[PAR].xm : ga[PAR].xp;
         if (ka >= lo_a1 && ka < n)
           gs(S3{}, S4{}, c, ga[PAR], Pf[S2::value * kSlot + c.own], odd ? gfw[S3::value].y : gfw[S3::value].x);
       }
-      if (d <= 2 && kb >= lo_b1 && kb < n)
-        gs(S2{}, S3{}, c, faces_b1(S2{}, c, a2f.zp, ga[PAR].zm), Pf[S1::value * kSlot + c.own],
-           odd ? gfw[S2::value].y : gfw[S2::value].x);
+      if (d <= 2 && kb >= lo_b1 && kb < n) {
+        Faces fb;
+        if constexpr (kXKeep) fb = faces_b1x(S2{}, c, a2f.zp, ga[PAR].zm, xgprev, odd);
+        else fb = faces_b1(S2{}, c, a2f.zp, ga[PAR].zm);
+        gs(S2{}, S3{}, c, fb, Pf[S1::value * kSlot + c.own], odd ? gfw[S2::value].y : gfw[S2::value].x);
+      }
       if (d <= 1 && kA >= lo_a2 && kA < n)
         gs(S1{}, S2{}, c, a2f, Pf[S0::value * kSlot + c.own], odd ? gfw[S1::value].y : gfw[S1::value].x);
     }
