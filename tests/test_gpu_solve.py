@@ -573,3 +573,45 @@ def test_from_rho_workspace_gives_the_same_bits(krylov):
         out.append((host(p), hist[:nh[0]].copy()))
         del ws
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+def test_fp64_fcg_from_rho_workspace_gives_the_same_bits():
+    """FP64 flexible CG at 256^3 on a workspace laid out with MG_FROM_RHO (a second
+    residual and a third direction: the residual update inside the preconditioner's
+    first pass, p updated every second step) against one without (their own passes,
+    p every step), NaN bit patterns in both: the same solution bit for bit, on solves
+    that end after an odd and after an even number of steps.  The residual norms of the
+    history are summed in another order (per workgroup of the two-sweep pass), so they
+    agree to rounding and give the same number of steps."""
+    import ctypes
+    from paper_1410_2240_amd import _lib
+    lib = _lib.load()
+    N = 256
+    inp, _ = workload("c2", N)
+    rho, mask, f = dev(inp.rho), dev(inp.mask), dev(inp.f)
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    steps = set()
+    for tol in (1e-10, 1e-6):
+        out = []
+        for flags in (_lib.MG_KRYLOV, _lib.MG_KRYLOV | _lib.MG_FROM_RHO):
+            size = lib.mg_workspace_size(_lib.dims3(N), flags)
+            ws = torch.full((size,), 0xFF, dtype=torch.uint8, device="cuda")
+            ctx = ctypes.c_void_p()
+            assert lib.mg_setup_from_rho(ctypes.byref(ctx), ctypes.c_void_p(ws.data_ptr()), size,
+                                         ctypes.c_void_p(rho.data_ptr()), ctypes.c_void_p(mask.data_ptr()),
+                                         _lib.dims3(N), 1.0 / N, flags, stream) == 0, _lib.last_error()
+            p = torch.zeros_like(f)
+            hist = np.zeros(101)
+            nh = (ctypes.c_int * 1)()
+            rc = lib.mg_solve(ctx, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(p.data_ptr()), 1, tol, 100,
+                              hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), nh, None)
+            lib.mg_destroy(ctx)
+            assert rc == 0, (flags, rc, _lib.last_error())
+            out.append((host(p), hist[:nh[0]].copy()))
+            del ws
+        steps.add(len(out[0][1]) - 1)
+        print(f"256^3 FP64 FCG to {tol:g}: {len(out[0][1]) - 1} steps", flush=True)
+        assert np.array_equal(out[0][0], out[1][0])
+        assert len(out[0][1]) == len(out[1][1])
+        assert np.allclose(out[0][1], out[1][1], rtol=1e-12, atol=0)
+    assert {s % 2 for s in steps} == {0, 1}, steps
